@@ -1,0 +1,299 @@
+"""Pins of the FP64 oracle against facts outside it (no GPU).
+
+Each test ties one oracle function to something it does not compute itself:
+an identity the paper proves (primal-plan BDRS / IPOT / O-BDRS forms, Lemma 1,
+Props. 1-3), an exact LP optimum, a closed form, arbitrary-precision brute
+force, or a value the paper prints.
+"""
+import json
+import math
+import os
+
+import mpmath
+import numpy as np
+import pytest
+
+from oracle import alg1, certificate, lp, lse, primal, repair
+from paper_2609_33814_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def small_problem(m, n, dim, seed, span=1.0):
+    return inputs.random_problem(m, n, dim, seed, span=span)
+
+
+# ----------------------------------------------------------------------------
+# LSE: arbitrary precision brute force and closed forms
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("eps", [1.0, 1e-2, 1e-4])
+def test_lse_matches_mpmath(eps):
+    p = small_problem(7, 11, 3, seed=5)
+    rng = np.random.default_rng(1)
+    w = rng.normal(0, 30, p.n)
+    got = lse.implicit_lse(p.x, p.y, p.cost_scale, eps, w)
+    mpmath.mp.dps = 50
+    for i in range(p.m):
+        terms = []
+        for j in range(p.n):
+            c = p.cost_scale * sum((mpmath.mpf(float(p.x[i, d])) - mpmath.mpf(float(p.y[j, d]))) ** 2
+                                   for d in range(3))
+            terms.append(mpmath.mpf(w[j]) - c / mpmath.mpf(eps))
+        ref = mpmath.log(mpmath.fsum(mpmath.exp(t) for t in terms))
+        assert abs(got[i] - float(ref)) <= 1e-12 * max(1.0, abs(float(ref)))
+
+
+def test_lse_closed_forms():
+    p = small_problem(5, 9, 2, seed=2)
+    w = np.linspace(-3, 2, p.n)
+    # zero cost: LSE_j(w_j) for every row
+    got = lse.implicit_lse(p.x, p.y, 0.0, 1.0, w)
+    assert np.allclose(got, math.log(sum(math.exp(v) for v in w)), rtol=0, atol=1e-13)
+    # a single column: the term itself
+    got1 = lse.implicit_lse(p.x, p.y[:1], p.cost_scale, 0.1, w[:1])
+    c = p.cost_scale * ((p.x.astype(np.float64) - p.y[0].astype(np.float64)) ** 2).sum(1)
+    assert np.allclose(got1, w[0] - c / 0.1, rtol=1e-14, atol=1e-12)
+    # all weights -inf: empty sum
+    assert np.all(lse.implicit_lse(p.x, p.y, p.cost_scale, 1.0, np.full(p.n, -np.inf)) == -np.inf)
+
+
+def test_lse_grid_separable_identity():
+    """On a grid the Gaussian kernel factorises over the two axes:
+    LSE_{(j1,j2)}(w - k((i1-j1)^2 + (i2-j2)^2)) = LSE_{j1}(-k(i1-j1)^2 + LSE_{j2}(w - k(i2-j2)^2)),
+    an O(n^1.5) evaluation that shares nothing with the tiled two-pass LSE."""
+    from scipy.special import logsumexp
+    side = 24
+    p = inputs.grid_problem(side, 3, 4)
+    eps = 0.003
+    rng = np.random.default_rng(9)
+    w = rng.normal(0, 50, p.n)
+    got = lse.implicit_lse(p.x, p.y, p.cost_scale, eps, w)
+    kap = p.cost_scale / eps
+    a = np.arange(side, dtype=np.float64)
+    G = -kap * (a[:, None] - a[None, :]) ** 2            # (i, j) along one axis
+    W = w.reshape(side, side)                           # (j1, j2)
+    inner = logsumexp(W[:, None, :] + G[None, :, :], axis=2)   # (j1, i2)
+    outer = logsumexp(inner[None, :, :] + G[:, :, None], axis=1)  # (i1, i2)
+    ref = outer.ravel()
+    assert np.max(np.abs(got - ref) / np.maximum(1, np.abs(ref))) < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1 against the primal-plan forms
+# ----------------------------------------------------------------------------
+def _state_plan_log(prob, st, eta, lam, k):
+    """log X^{k+1} = log alpha^k + log beta^k - lambda (k+1) C / eta (Lemma 1, Prop. 2)."""
+    C = lse.cost_matrix(prob.x, prob.y, prob.cost_scale)
+    return st.la[:, None] + st.lb1[None, :] - lam * (k + 1) * C / eta
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_dual_bdrs_equals_primal_bdrs(seed):
+    p = small_problem(9, 12, 2, seed)
+    eta, iters = 1.0, 60
+    C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+    Xs, us, vs = primal.bdrs_primal(C, p.r, p.c, eta, iters)
+    _, _, states = alg1.run(p, eta, 1.0, iters, keep_states=True)
+    la_cum = np.zeros(p.m)
+    for k, st in enumerate(states):
+        lX = _state_plan_log(p, st, eta, 1.0, k)
+        ref = np.log(Xs[k + 1])
+        assert np.max(np.abs(lX - ref) / np.maximum(1, np.abs(ref))) < 1e-11, k
+        la_cum += np.log(us[k])       # a^k = prod_t u^t (Lemma 1)
+        assert np.allclose(st.la, la_cum, rtol=1e-11, atol=1e-11)
+        # column feasibility of X^{k+1} (Sec. 2)
+        assert np.allclose(np.exp(lX).sum(axis=0), p.c, rtol=1e-11, atol=0)
+
+
+def test_primal_bdrs_equals_ipot_single_inner_step():
+    p = small_problem(8, 10, 2, 3)
+    C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+    Xs, _, _ = primal.bdrs_primal(C, p.r, p.c, 0.7, 40)
+    Gs = primal.ipot(C, p.r, p.c, 0.7, 40, inner=1)
+    for X, G in zip(Xs, Gs):
+        assert np.allclose(X, G, rtol=1e-11, atol=0)
+    # more inner steps is a different method: the sequences must separate
+    G3 = primal.ipot(C, p.r, p.c, 0.7, 40, inner=3)
+    assert not np.allclose(Xs[5], G3[5], rtol=1e-6)
+
+
+@pytest.mark.parametrize("lam", [1.2, 1.5, 1.99])
+def test_dual_obdrs_equals_primal_obdrs(lam):
+    p = small_problem(8, 11, 3, 7)
+    eta, iters = 1.0, 50
+    C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+    Xs, us, vs = primal.obdrs_primal(C, p.r, p.c, eta, lam, iters)
+    _, _, states = alg1.run(p, eta, lam, iters, keep_states=True)
+    la_prev = np.zeros(p.m)
+    la_sum = np.zeros(p.m)
+    for k, st in enumerate(states):
+        lX = _state_plan_log(p, st, eta, lam, k)
+        ref = np.log(Xs[k + 1])
+        assert np.max(np.abs(lX - ref) / np.maximum(1, np.abs(ref))) < 1e-10, k
+        # log alpha-hat^k = log alpha^{k-1} + log u^k; log alpha^k = lambda sum_t log u^t
+        assert np.allclose(st.lah, la_prev + np.log(us[k]), rtol=1e-10, atol=1e-10)
+        la_sum += np.log(us[k])
+        assert np.allclose(st.la, lam * la_sum, rtol=1e-10, atol=1e-10)
+        la_prev = st.la
+
+
+def test_primal_obdrs_at_lambda_one_is_bdrs():
+    p = small_problem(6, 7, 2, 8)
+    C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+    A = primal.bdrs_primal(C, p.r, p.c, 1.0, 30)[0]
+    B = primal.obdrs_primal(C, p.r, p.c, 1.0, 1.0, 30)[0]
+    for a, b in zip(A, B):
+        assert np.allclose(a, b, rtol=1e-12, atol=0)
+
+
+# ----------------------------------------------------------------------------
+# Schedule numbers printed in the matched-temperature ablation
+# ----------------------------------------------------------------------------
+def test_schedule_table2b():
+    g = json.load(open(os.path.join(GOLDEN, "table2b_schedule.json")))
+    T = g["T"]
+    for pr in g["pairs"]:
+        lam = pr["lambda"]
+        eps_O = alg1.schedule(1.0, lam, T)
+        eta_B = pr["eta_B_num"] / pr["eta_B_den"]
+        eps_B = alg1.schedule(eta_B, 1.0, T)
+        assert abs(eps_O - eps_B) <= 1e-18
+        assert abs(eps_O - pr["eps_K_printed"]) <= 0.005e-6
+        assert abs(eta_B - (T + 1) / (lam * T + 1)) < 1e-15
+    assert math.floor(g["regime1_k"] / g["regime1_lambda"]) == g["regime1_kO_printed"]
+
+
+# ----------------------------------------------------------------------------
+# Certificate: brackets and invariants
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("lam", [1.0, 1.2, 1.5, 1.99])
+def test_certificate_brackets_bruteforce_optimum(lam):
+    for seed in range(3):
+        n = 6
+        p = small_problem(n, n, 2, 100 + seed)
+        p.r[:] = 1.0 / n
+        p.c[:] = 1.0 / n
+        C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+        pstar = lp.brute_force_uniform(C)
+        _, certs, _ = alg1.run(p, 1.0, lam, 120, cert_every=7)
+        for ce in certs:
+            assert ce["L"] <= pstar + 1e-12
+            assert ce["U"] >= pstar - 1e-12
+        assert certs[-1]["gap"] < 0.05
+
+
+@pytest.mark.parametrize("lam", [1.0, 1.99])
+def test_certificate_brackets_lp_optimum(lam):
+    p = small_problem(14, 17, 3, 21)
+    C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+    pstar = lp.linprog_ot(C, p.r, p.c)
+    _, certs, _ = alg1.run(p, 0.5, lam, 600, cert_every=25)
+    for ce in certs:
+        assert ce["L"] <= pstar + 1e-10 and pstar <= ce["U"] + 1e-10
+    assert certs[-1]["U_best"] - certs[-1]["L_best"] < 1e-3
+
+
+def test_certificate_brackets_exact_1d_optimum():
+    rng = np.random.default_rng(4)
+    m, n = 300, 250
+    x = rng.random((m, 1)).astype(np.float32)
+    y = (rng.random((n, 1)) ** 2).astype(np.float32)
+    r = rng.uniform(0.5, 1.5, m); r /= r.sum()
+    c = rng.uniform(0.5, 1.5, n); c /= c.sum()
+    p = inputs.Problem(x=x, y=y, r=r, c=c, cost_scale=1.0)
+    pstar = lp.sorted_1d(x, y, r, c, 1.0)
+    _, certs, _ = alg1.run(p, 0.3, 1.0, 200, cert_every=50)
+    for ce in certs:
+        assert ce["L"] <= pstar + 1e-12 <= ce["U"] + 2e-12
+
+
+def test_lp_references_agree():
+    for seed in range(3):
+        p = small_problem(6, 6, 2, 300 + seed)
+        u = np.full(6, 1 / 6)
+        C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+        assert abs(lp.brute_force_uniform(C) - lp.linprog_ot(C, u, u)) < 1e-9
+    rng = np.random.default_rng(8)
+    x, y = rng.random(13), rng.random(9)
+    r = rng.uniform(0.5, 1, 13); r /= r.sum()
+    c = rng.uniform(0.5, 1, 9); c /= c.sum()
+    C = (x[:, None] - y[None, :]) ** 2
+    assert abs(lp.sorted_1d(x, y, r, c, 1.0) - lp.linprog_ot(C, r, c)) < 1e-9
+
+
+@pytest.mark.parametrize("lam", [1.0, 1.5])
+def test_certificate_invariants(lam):
+    p = small_problem(12, 15, 2, 33)
+    C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+    eta = 1.0
+    st, _, _ = alg1.run(p, eta, lam, 40)
+    k = st.k - 1
+    eps = alg1.schedule(eta, lam, k)
+    ce = certificate.certificate(p.x, p.y, p.cost_scale, p.r, p.c, st.lah, st.lbh, st.lt, eps)
+    Z = np.exp(st.lah[:, None] - C / eps + st.lt[None, :])
+    assert np.allclose(Z.sum(axis=1), p.r, rtol=1e-12)            # Z 1 = r
+    assert abs(ce["s"].sum() - 1.0) < 1e-12                       # 1^T s = 1
+    assert np.allclose(ce["s"], Z.sum(axis=0), rtol=1e-11)        # s = Z^T 1
+    assert np.allclose(ce["s"], p.c * np.exp(st.lt - st.lbh), rtol=1e-11)  # s = c t / B
+    assert np.all(ce["f"][:, None] + ce["g"][None, :] <= C + 1e-13)  # dual feasible
+    assert np.all(ce["D"] >= 1.0 - 1e-15) and np.all(ce["D"] <= p.m)
+    assert np.all(ce["mu"] >= C.min(axis=0) - 1e-15) and np.all(ce["mu"] <= C.max(axis=0) + 1e-15)
+    assert abs(ce["cost_Z"] - (C * Z).sum()) < 1e-13            # <t, w> = <C, Z>
+    w = ((C * np.exp(-C / eps)).T @ np.exp(st.lah))
+    assert abs(np.dot(np.exp(st.lt), w) - ce["cost_Z"]) < 1e-12
+
+
+def test_worked_underflow_example():
+    g = json.load(open(os.path.join(GOLDEN, "underflow_example.json")))
+    # two sources at distance 1 from a single target in 1-D: C_1j = C_2j = 1
+    x = np.array([[-1.0], [1.0]], dtype=np.float32)
+    y = np.array([[0.0]], dtype=np.float32)
+    lah = np.log(np.array(g["A"]))
+    with np.errstate(under="ignore"):
+        naive = np.exp(lah - np.array(g["C_col"]) / g["eps"])
+    assert np.all(naive == 0.0)                  # the unshifted weights underflow
+    M, D, N = certificate.column_statistics(x, y, 1.0, g["eps"], lah)
+    assert D[0] == g["D"] and N[0] / D[0] == g["mu"]
+    assert np.all(np.isfinite([M[0], D[0], N[0]]))
+
+
+# ----------------------------------------------------------------------------
+# Feasible repair
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("lam", [1.0, 1.99])
+def test_dense_repair_is_feasible_and_bracketed(lam):
+    p = small_problem(10, 13, 2, 41)
+    C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+    pstar = lp.linprog_ot(C, p.r, p.c)
+    eta = 1.0
+    for iters in (3, 25, 80):
+        st, _, _ = alg1.run(p, eta, lam, iters)
+        eps = alg1.schedule(eta, lam, st.k - 1)
+        ce = certificate.certificate(p.x, p.y, p.cost_scale, p.r, p.c, st.lah, st.lbh, st.lt, eps)
+        rp = repair.dense_repair(p.x, p.y, p.cost_scale, p.r, p.c, st.lah, st.lt, eps)
+        Zh = rp["Zhat"]
+        assert np.all(Zh >= -1e-13)
+        assert np.allclose(Zh.sum(axis=1), p.r, rtol=1e-11, atol=1e-15)
+        assert np.allclose(Zh.sum(axis=0), p.c, rtol=1e-11, atol=1e-15)
+        assert np.all(rp["p"] >= -1e-13) and np.all(rp["q"] >= -1e-13)  # r - Z~1 cancels
+        assert abs(rp["p"].sum() - rp["delta"]) < 1e-13 and abs(rp["q"].sum() - rp["delta"]) < 1e-13
+        assert abs(rp["delta"] - ce["delta"]) < 1e-13
+        osc = C.max() - C.min()
+        assert rp["cost_Zhat"] - rp["cost_Z"] <= osc * rp["delta"] + 1e-13
+        assert ce["L"] <= pstar + 1e-12 <= rp["cost_Zhat"] + 2e-12 <= ce["U"] + 3e-12
+        imp = repair.implicit_repair(p.x, p.y, p.cost_scale, p.r, p.c, st.lah, st.lt, eps,
+                                     ce["s"], ce["mu"])
+        assert abs(imp["cost_Zhat"] - rp["cost_Zhat"]) < 1e-12
+        assert np.allclose(imp["p"], rp["p"], rtol=1e-9, atol=1e-14)  # dense p = r - Z~1 cancels
+
+
+def test_generators_are_valid_problems():
+    p = inputs.c1_problem()
+    assert p.m == p.n == 1024 and p.dim == 2
+    assert abs(p.r.sum() - 1) < 1e-12 and abs(p.c.sum() - 1) < 1e-12
+    assert p.r.min() > 0 and p.c.min() > 0
+    C = lse.cost_block(p.x[[0, 1023]], p.y, p.cost_scale)
+    assert C.max() == 1.0                       # opposite corners cost exactly 1
+    q = inputs.colour_problem(3000, 2000, 31, 32)
+    C = lse.cost_matrix(q.x, q.y, q.cost_scale)
+    assert abs(C.max() - 1.0) < 1e-12 and C.min() >= 0
