@@ -1,0 +1,207 @@
+"""ctypes binding of libbdrs.so (include/bdrs.h): argument marshalling only.
+
+Every step of the solver runs in the library's HIP kernels; PyTorch only
+supplies device memory (the workspace and the input/output tensors) and the
+stream.  There is no fallback: if the library is missing, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libbdrs.so")
+
+OK, NOT_CONVERGED = 0, 1
+E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_NUMERIC = -1, -2, -3, -4, -5
+F_REPAIR = 1
+
+EXPORTS = [
+    "bdrs_workspace_size", "bdrs_create", "bdrs_step", "bdrs_certificate", "bdrs_solve",
+    "bdrs_get_state", "bdrs_set_state", "bdrs_lse", "bdrs_destroy", "bdrs_last_error",
+    "bdrs_version", "bdrs_profile", "bdrs_profile_read",
+]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("dim", ctypes.c_int32),
+        ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+        ("r", ctypes.c_void_p), ("c", ctypes.c_void_p),
+        ("cost_scale", ctypes.c_double), ("eta", ctypes.c_double),
+        ("lambda_", ctypes.c_double), ("omega", ctypes.c_double),
+        ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p), ("flags", ctypes.c_uint32),
+    ]
+
+
+class Cert(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int64), ("eps", ctypes.c_double), ("L", ctypes.c_double),
+        ("U", ctypes.c_double), ("gap", ctypes.c_double), ("rel_gap", ctypes.c_double),
+        ("L_best", ctypes.c_double), ("U_best", ctypes.c_double),
+        ("rel_gap_best", ctypes.c_double), ("k_L_best", ctypes.c_int64),
+        ("k_U_best", ctypes.c_int64), ("delta", ctypes.c_double),
+        ("cost_Z", ctypes.c_double), ("repaired_cost", ctypes.c_double),
+        ("n_nonfinite", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class BdrsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"bdrs status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libbdrs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2609_33814_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        L.bdrs_workspace_size.argtypes = [P(Params), P(ctypes.c_size_t)]
+        L.bdrs_create.argtypes = [P(Params), P(vp)]
+        L.bdrs_step.argtypes = [vp, ctypes.c_int32]
+        L.bdrs_certificate.argtypes = [vp, P(Cert)]
+        L.bdrs_solve.argtypes = [vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_int32, P(Cert)]
+        L.bdrs_get_state.argtypes = [vp] * 7 + [P(ctypes.c_int64)]
+        L.bdrs_set_state.argtypes = [vp] * 7 + [ctypes.c_int64]
+        L.bdrs_lse.argtypes = [vp, ctypes.c_int32, ctypes.c_double, vp, vp]
+        L.bdrs_destroy.argtypes = [vp]
+        L.bdrs_profile.argtypes = [vp, ctypes.c_int32]
+        L.bdrs_profile_read.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_double), P(ctypes.c_double)]
+        L.bdrs_last_error.restype = ctypes.c_char_p
+        L.bdrs_version.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("bdrs_last_error", "bdrs_version"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().bdrs_last_error().decode()
+
+
+def check(status: int, allow=(OK,)) -> int:
+    if status not in allow:
+        raise BdrsError(status, last_error())
+    return status
+
+
+def make_params(m, n, dim, x=0, y=0, r=0, c=0, cost_scale=1.0, eta=1.0, lam=1.0,
+                omega=1.0, workspace=0, workspace_bytes=0, stream=0, flags=0) -> Params:
+    return Params(m, n, dim, x, y, r, c, cost_scale, eta, lam, omega, workspace,
+                  workspace_bytes, stream, flags)
+
+
+def workspace_size(m: int, n: int, dim: int) -> int:
+    out = ctypes.c_size_t()
+    p = make_params(m, n, dim)
+    check(lib().bdrs_workspace_size(ctypes.byref(p), ctypes.byref(out)))
+    return out.value
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+class Solver:
+    """One OT problem on the current device; inputs are torch tensors on the GPU.
+
+    x (m, d) float32, y (n, d) float32, r (m,) float64, c (n,) float64.
+    """
+
+    def __init__(self, x, y, r, c, cost_scale, eta=1.0, lam=1.0, omega=1.0,
+                 stream=None, repair=False):
+        import torch
+        self._torch = torch
+        m, dim = int(x.shape[0]), int(x.shape[1])
+        n = int(y.shape[0])
+        self.m, self.n, self.dim = m, n, dim
+        self.bytes = workspace_size(m, n, dim)
+        # 256-byte aligned workspace carved out of a torch allocation
+        self._ws = torch.empty(self.bytes + 256, dtype=torch.uint8, device=x.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self._stream = stream if stream is not None else torch.cuda.current_stream(x.device)
+        self._inputs = (x.contiguous(), y.contiguous(), r.contiguous(), c.contiguous())
+        xx, yy, rr, cc = self._inputs
+        self.params = make_params(m, n, dim, _ptr(xx), _ptr(yy), _ptr(rr), _ptr(cc),
+                                  float(cost_scale), float(eta), float(lam), float(omega),
+                                  self._ws_ptr, self.bytes, int(self._stream.cuda_stream),
+                                  F_REPAIR if repair else 0)
+        h = ctypes.c_void_p()
+        check(lib().bdrs_create(ctypes.byref(self.params), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def step(self, iters: int) -> None:
+        check(lib().bdrs_step(self._h, int(iters)))
+
+    def certificate(self) -> dict:
+        ce = Cert()
+        check(lib().bdrs_certificate(self._h, ctypes.byref(ce)))
+        return ce.as_dict()
+
+    def solve(self, tau: float, max_iters: int, cert_every: int, relative: bool = True):
+        ce = Cert()
+        st = check(lib().bdrs_solve(self._h, float(tau), 1 if relative else 0, int(max_iters),
+                                    int(cert_every), ctypes.byref(ce)), allow=(OK, NOT_CONVERGED))
+        return st == OK, ce.as_dict()
+
+    def get_state(self) -> dict:
+        torch = self._torch
+        dev = self._inputs[0].device
+        la = torch.empty(self.m, dtype=torch.float32, device=dev)
+        lah = torch.empty_like(la)
+        lb, lb1, lbh, lt = (torch.empty(self.n, dtype=torch.float32, device=dev) for _ in range(4))
+        k = ctypes.c_int64()
+        check(lib().bdrs_get_state(self._h, _ptr(la), _ptr(lb), _ptr(lb1), _ptr(lah), _ptr(lbh),
+                                   _ptr(lt), ctypes.byref(k)))
+        return dict(la=la, lb=lb, lb_prev=lb1, lah=lah, lbh=lbh, lt=lt, k=k.value)
+
+    def set_state(self, st: dict) -> None:
+        f = lambda key: None if st.get(key) is None else st[key].contiguous()
+        keep = [f(key) for key in ("la", "lb", "lb_prev", "lah", "lbh", "lt")]
+        check(lib().bdrs_set_state(self._h, *[_ptr(t) for t in keep], int(st["k"])))
+
+    def lse(self, w, eps: float, transpose: bool = False):
+        """out_i = LSE_j(w_j - C_ij/eps) (or the transposed reduction), float32."""
+        torch = self._torch
+        w = w.contiguous()
+        out = torch.empty(self.n if transpose else self.m, dtype=torch.float32, device=w.device)
+        check(lib().bdrs_lse(self._h, 1 if transpose else 0, float(eps), _ptr(w), _ptr(out)))
+        return out
+
+    def profile(self, enable: bool) -> None:
+        check(lib().bdrs_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        n, ms, ent = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        check(lib().bdrs_profile_read(self._h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(ent)))
+        return dict(sweeps=n.value, ms=ms.value, entries=ent.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().bdrs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,704 @@
+// Host runtime behind the C ABI of include/bdrs.h.
+//
+// Responsibilities: argument checks (host only, before any HIP call), the
+// layout of the caller's device workspace, the tile order of the points
+// (Morton order, so that each 64-point tile is spatially compact), and the
+// iteration / certificate loop of Algorithm 1 with the best-bound stopping
+// rule.
+#include "bdrs_internal.h"
+#include "../../include/bdrs.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using namespace bdrs;
+
+namespace {
+
+thread_local std::string g_err;
+
+bdrs_status fail(bdrs_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(BDRS_E_DEVICE, "HIP error %s in %s", hipGetErrorString(e_), #expr);     \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct SideShape {
+  int count, ntiles, np;
+};
+
+SideShape side_shape(int count) {
+  SideShape s;
+  s.count = count;
+  s.ntiles = (count + kTile - 1) / kTile;
+  s.np = (s.ntiles * kTile + kBlock - 1) / kBlock * kBlock;
+  return s;
+}
+
+// Offsets of every sub-buffer inside the workspace.
+struct Layout {
+  SideShape R, C;
+  int splits_row, splits_col, splits_max;
+  int cert_blocks;
+  size_t total;
+  // offsets
+  size_t ctrl;
+  size_t r_abs, r_off, r_hdr, r_A, r_Amax, r_perm, r_marg, r_logm;
+  size_t c_abs, c_off, c_hdr, c_A, c_Amax, c_perm, c_marg, c_logm;
+  size_t la, lah, lb1, lb2, lbh, lt0, lt1, mu, logs, pvec;
+  size_t pM, pS, pN, cert_part, cert_out;
+};
+
+Layout make_layout(int m, int n, int dim) {
+  Layout L{};
+  L.R = side_shape(m);
+  L.C = side_shape(n);
+  L.splits_row = choose_splits(L.R.np, L.C.ntiles);
+  L.splits_col = choose_splits(L.C.np, L.R.ntiles);
+  L.splits_max = std::max(L.splits_row, L.splits_col);
+  const int npmax = std::max(L.R.np, L.C.np);
+  L.cert_blocks = std::max(1, std::min(256, npmax / kBlock));
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.ctrl = take(sizeof(Ctrl));
+  auto side = [&](const SideShape& s, size_t& abs, size_t& off, size_t& hdr, size_t& A, size_t& Amax,
+                  size_t& perm, size_t& marg, size_t& logm) {
+    abs = take(sizeof(float) * (size_t)dim * s.np);
+    off = take(sizeof(float) * (size_t)s.ntiles * dim * kTile);
+    hdr = take(sizeof(float) * (size_t)s.ntiles * kHdr);
+    A = take(sizeof(float) * (size_t)s.np);
+    Amax = take(sizeof(float) * (size_t)s.ntiles);
+    perm = take(sizeof(int) * (size_t)s.np);
+    marg = take(sizeof(double) * (size_t)s.np);
+    logm = take(sizeof(double) * (size_t)s.np);
+  };
+  side(L.R, L.r_abs, L.r_off, L.r_hdr, L.r_A, L.r_Amax, L.r_perm, L.r_marg, L.r_logm);
+  side(L.C, L.c_abs, L.c_off, L.c_hdr, L.c_A, L.c_Amax, L.c_perm, L.c_marg, L.c_logm);
+  L.la = take(sizeof(float) * L.R.np);
+  L.lah = take(sizeof(float) * L.R.np);
+  L.lb1 = take(sizeof(float) * L.C.np);
+  L.lb2 = take(sizeof(float) * L.C.np);
+  L.lbh = take(sizeof(float) * L.C.np);
+  L.lt0 = take(sizeof(float) * L.C.np);
+  L.lt1 = take(sizeof(float) * L.C.np);
+  L.mu = take(sizeof(double) * L.C.np);
+  L.logs = take(sizeof(double) * L.C.np);
+  L.pvec = take(sizeof(double) * L.R.np);
+  const size_t pelems = (size_t)std::max((size_t)L.splits_row * L.R.np, (size_t)L.splits_col * L.C.np);
+  L.pM = take(sizeof(float) * pelems);
+  L.pS = take(sizeof(float) * pelems);
+  L.pN = take(sizeof(float) * pelems);
+  L.cert_part = take(sizeof(double) * 2 * (size_t)L.cert_blocks * 8);
+  L.cert_out = take(sizeof(double) * kCertSlots);
+  L.total = o;
+  return L;
+}
+
+bdrs_status check_sizes(const bdrs_params* p) {
+  if (!p) return fail(BDRS_E_INVALID, "params is NULL");
+  if (p->m < 1 || p->m > (1 << 30)) return fail(BDRS_E_INVALID, "m out of range [1, 2^30]: %d", p->m);
+  if (p->n < 1 || p->n > (1 << 30)) return fail(BDRS_E_INVALID, "n out of range [1, 2^30]: %d", p->n);
+  if (p->dim < 1 || p->dim > 3) return fail(BDRS_E_INVALID, "dim must be 1, 2 or 3: %d", p->dim);
+  return BDRS_OK;
+}
+
+bdrs_status check_params(const bdrs_params* p) {
+  bdrs_status st = check_sizes(p);
+  if (st != BDRS_OK) return st;
+  if (!p->x) return fail(BDRS_E_INVALID, "x is NULL");
+  if (!p->y) return fail(BDRS_E_INVALID, "y is NULL");
+  if (!p->r) return fail(BDRS_E_INVALID, "r is NULL");
+  if (!p->c) return fail(BDRS_E_INVALID, "c is NULL");
+  if (!(std::isfinite(p->cost_scale) && p->cost_scale > 0))
+    return fail(BDRS_E_INVALID, "cost_scale must be finite and > 0");
+  if (!(std::isfinite(p->eta) && p->eta > 0)) return fail(BDRS_E_INVALID, "eta must be finite and > 0");
+  if (!(p->lambda >= 1.0 && p->lambda < 2.0)) return fail(BDRS_E_INVALID, "lambda must lie in [1, 2)");
+  if (!(std::isfinite(p->omega) && p->omega >= 0)) return fail(BDRS_E_INVALID, "omega must be finite and >= 0");
+  if (p->flags & ~BDRS_F_REPAIR) return fail(BDRS_E_INVALID, "unknown flags 0x%x", p->flags);
+  if (!p->workspace) return fail(BDRS_E_INVALID, "workspace is NULL");
+  if (((uintptr_t)p->workspace) % kAlign) return fail(BDRS_E_INVALID, "workspace must be 256-byte aligned");
+  const Layout L = make_layout(p->m, p->n, p->dim);
+  if (p->workspace_bytes < L.total)
+    return fail(BDRS_E_NOMEM, "workspace too small: %zu bytes given, %zu needed", p->workspace_bytes, L.total);
+  return BDRS_OK;
+}
+
+bdrs_status check_device() {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count < 1) return fail(BDRS_E_DEVICE, "no HIP device available");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(BDRS_E_DEVICE, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+  return BDRS_OK;
+}
+
+// 21-bit-per-axis Morton code of a point quantised over the side's bounding box.
+uint64_t spread3(uint64_t v) {
+  v &= 0x1fffff;
+  v = (v | v << 32) & 0x1f00000000ffffull;
+  v = (v | v << 16) & 0x1f0000ff0000ffull;
+  v = (v | v << 8) & 0x100f00f00f00f00full;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+  v = (v | v << 2) & 0x1249249249249249ull;
+  return v;
+}
+uint64_t spread2(uint64_t v) {
+  v &= 0xffffffffull;
+  v = (v | v << 16) & 0x0000ffff0000ffffull;
+  v = (v | v << 8) & 0x00ff00ff00ff00ffull;
+  v = (v | v << 4) & 0x0f0f0f0f0f0f0f0full;
+  v = (v | v << 2) & 0x3333333333333333ull;
+  v = (v | v << 1) & 0x5555555555555555ull;
+  return v;
+}
+
+struct HostSide {
+  std::vector<float> abs, off, hdr;
+  std::vector<int> perm;
+  std::vector<double> marg, logm;
+};
+
+void build_side(const std::vector<float>& pts, const std::vector<double>& w, int count, int dim,
+                const double origin[3], const SideShape& sh, HostSide& hs) {
+  // tile order: Morton order of the quantised coordinates
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int d = 0; d < dim; ++d) {
+    lo[d] = hi[d] = pts[d];
+    for (int i = 0; i < count; ++i) {
+      lo[d] = std::min(lo[d], (double)pts[(size_t)i * dim + d]);
+      hi[d] = std::max(hi[d], (double)pts[(size_t)i * dim + d]);
+    }
+  }
+  const int bits = dim == 1 ? 31 : (dim == 2 ? 31 : 21);
+  const double qmax = (double)((1u << bits) - 1);
+  std::vector<uint64_t> code(count);
+  for (int i = 0; i < count; ++i) {
+    uint64_t q[3] = {0, 0, 0};
+    for (int d = 0; d < dim; ++d) {
+      const double span = hi[d] - lo[d];
+      q[d] = span > 0 ? (uint64_t)std::llround((pts[(size_t)i * dim + d] - lo[d]) / span * qmax) : 0;
+    }
+    code[i] = dim == 1 ? q[0] : (dim == 2 ? (spread2(q[0]) | spread2(q[1]) << 1)
+                                          : (spread3(q[0]) | spread3(q[1]) << 1 | spread3(q[2]) << 2));
+  }
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return code[a] < code[b]; });
+
+  hs.perm.assign(sh.np, order[count - 1]);
+  for (int s = 0; s < count; ++s) hs.perm[s] = order[s];
+  hs.abs.assign((size_t)dim * sh.np, 0.f);
+  for (int s = 0; s < sh.np; ++s) {
+    const int i = hs.perm[s];
+    for (int d = 0; d < dim; ++d) hs.abs[(size_t)d * sh.np + s] = (float)((double)pts[(size_t)i * dim + d] - origin[d]);
+  }
+  hs.marg.assign(sh.np, 0.0);
+  hs.logm.assign(sh.np, -INFINITY);
+  for (int s = 0; s < count; ++s) {
+    hs.marg[s] = w[hs.perm[s]];
+    hs.logm[s] = std::log(w[hs.perm[s]]);
+  }
+  hs.off.assign((size_t)sh.ntiles * dim * kTile, 0.f);
+  hs.hdr.assign((size_t)sh.ntiles * kHdr, 0.f);
+  for (int t = 0; t < sh.ntiles; ++t) {
+    const int s0 = t * kTile, s1 = std::min(count, s0 + kTile);
+    for (int d = 0; d < dim; ++d) {
+      float mn = hs.abs[(size_t)d * sh.np + s0], mx = mn;
+      for (int s = s0; s < s1; ++s) {
+        mn = std::min(mn, hs.abs[(size_t)d * sh.np + s]);
+        mx = std::max(mx, hs.abs[(size_t)d * sh.np + s]);
+      }
+      const float ctr = 0.5f * (mn + mx);
+      float rad = 0.f;
+      for (int s = s0; s < s0 + kTile; ++s) {
+        const float b = hs.abs[(size_t)d * sh.np + s] - ctr;
+        hs.off[((size_t)t * dim + d) * kTile + (s - s0)] = b;
+        if (s < s1) rad = std::max(rad, std::fabs(b));
+      }
+      hs.hdr[(size_t)t * kHdr + d] = ctr;
+      hs.hdr[(size_t)t * kHdr + 3 + d] = rad;
+    }
+  }
+}
+
+}  // namespace
+
+struct bdrs_solver_ {
+  bdrs_params prm;
+  Layout L;
+  LaunchCtx ctx;
+  long long k = 0;          // finished iterations (mirrors Ctrl::k)
+  double U_best = INFINITY, L_best = -INFINITY;
+  long long kU = -1, kL = -1;
+  bool packed_rows = false; // rows.A holds log alpha-hat of iteration k-1
+  // sweep timing (bdrs_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;  // created on demand, reused after each read
+  size_t ev_used = 0;
+  double prof_entries = 0.0;
+  long long prof_sweeps = 0;
+};
+
+namespace {
+
+void fill_ctx(bdrs_solver s) {
+  const Layout& L = s->L;
+  char* base = (char*)s->prm.workspace;
+  LaunchCtx& c = s->ctx;
+  c.stream = (hipStream_t)s->prm.stream;
+  c.dim = s->prm.dim;
+  c.ctrl = (Ctrl*)(base + L.ctrl);
+  auto side = [&](SideDev& sd, const SideShape& sh, size_t abs, size_t off, size_t hdr, size_t A, size_t Amax,
+                  size_t perm, size_t marg, size_t logm) {
+    sd.count = sh.count;
+    sd.ntiles = sh.ntiles;
+    sd.np = sh.np;
+    sd.pad = 0;
+    sd.abs = (float*)(base + abs);
+    sd.off = (float*)(base + off);
+    sd.hdr = (float*)(base + hdr);
+    sd.A = (float*)(base + A);
+    sd.Amax = (float*)(base + Amax);
+    sd.perm = (int*)(base + perm);
+    sd.marg = (double*)(base + marg);
+    sd.logmarg = (double*)(base + logm);
+  };
+  side(c.rows, L.R, L.r_abs, L.r_off, L.r_hdr, L.r_A, L.r_Amax, L.r_perm, L.r_marg, L.r_logm);
+  side(c.cols, L.C, L.c_abs, L.c_off, L.c_hdr, L.c_A, L.c_Amax, L.c_perm, L.c_marg, L.c_logm);
+  c.st.la = (float*)(base + L.la);
+  c.st.lah = (float*)(base + L.lah);
+  c.st.lb1 = (float*)(base + L.lb1);
+  c.st.lb2 = (float*)(base + L.lb2);
+  c.st.lbh = (float*)(base + L.lbh);
+  c.st.lt[0] = (float*)(base + L.lt0);
+  c.st.lt[1] = (float*)(base + L.lt1);
+  c.st.mu = (double*)(base + L.mu);
+  c.st.logs = (double*)(base + L.logs);
+  c.st.pvec = (double*)(base + L.pvec);
+  c.part.M = (float*)(base + L.pM);
+  c.part.S = (float*)(base + L.pS);
+  c.part.N = (float*)(base + L.pN);
+  c.part.splits = L.splits_max;
+  c.cert_part = (double*)(base + L.cert_part);
+  c.cert_out = (double*)(base + L.cert_out);
+  c.cert_blocks = L.cert_blocks;
+}
+
+double eps_at(const bdrs_solver s, long long k) { return s->prm.eta / (s->prm.lambda * (double)k + 1.0); }
+
+bdrs_status hip_status(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(BDRS_E_DEVICE, "HIP error %s in %s", hipGetErrorString(e), what);
+  return BDRS_OK;
+}
+
+// one LSE sweep launch, bracketed by HIP events when profiling is on
+hipError_t sweep(bdrs_solver s, bool transpose, bool cert, int splits, double eps_arg) {
+  if (!s->prof) return launch_sweep(s->ctx, transpose, cert, splits, eps_arg);
+  while (s->ev_pool.size() < s->ev_used + 2) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    s->ev_pool.push_back(ev);
+  }
+  hipEvent_t a = s->ev_pool[s->ev_used], b = s->ev_pool[s->ev_used + 1];
+  hipError_t e = hipEventRecord(a, s->ctx.stream);
+  if (e == hipSuccess) e = launch_sweep(s->ctx, transpose, cert, splits, eps_arg);
+  if (e == hipSuccess) e = hipEventRecord(b, s->ctx.stream);
+  if (e == hipSuccess) {
+    s->ev_used += 2;
+    s->prof_sweeps += 1;
+    s->prof_entries += (double)s->prm.m * (double)s->prm.n;
+  }
+  return e;
+}
+
+// one iteration of Algorithm 1; with cert the column sweep also gathers Algorithm 2's statistics
+bdrs_status enqueue_iteration(bdrs_solver s, bool cert) {
+  const LaunchCtx& c = s->ctx;
+  hipError_t e;
+  if ((e = sweep(s, false, false, s->L.splits_row, -1.0)) != hipSuccess) return hip_status(e, "row sweep");
+  if ((e = launch_finish(c, false, kFinishRow, s->L.splits_row, -1.0, nullptr)) != hipSuccess)
+    return hip_status(e, "row finish");
+  if ((e = sweep(s, true, cert, s->L.splits_col, -1.0)) != hipSuccess) return hip_status(e, "col sweep");
+  if ((e = launch_finish(c, true, cert ? kFinishColCert : kFinishCol, s->L.splits_col, -1.0, nullptr)) != hipSuccess)
+    return hip_status(e, "col finish");
+  s->k += 1;
+  s->packed_rows = true;
+  return BDRS_OK;
+}
+
+// re-derives the packed sweep weights from the dual state (after bdrs_lse or a repair pass)
+bdrs_status repack(bdrs_solver s) {
+  const LaunchCtx& c = s->ctx;
+  hipError_t e;
+  if ((e = launch_prologue(c)) != hipSuccess) return hip_status(e, "prologue");
+  if (s->k > 0) {
+    // rows.A <- log alpha-hat of iteration k-1 with that iteration's temperature
+    if ((e = launch_pack_rows_from_lah(c, eps_at(s, s->k - 1))) != hipSuccess) return hip_status(e, "repack");
+    s->packed_rows = true;
+  }
+  return BDRS_OK;
+}
+
+bdrs_status read_cert(bdrs_solver s, bool repair, bdrs_cert* out) {
+  double h[kCertSlots];
+  HIPCHK(hipMemcpyAsync(h, s->ctx.cert_out, sizeof h, hipMemcpyDeviceToHost, s->ctx.stream));
+  HIPCHK(hipStreamSynchronize(s->ctx.stream));
+  bdrs_cert ce;
+  ce.k = (int64_t)h[0];
+  ce.eps = h[1];
+  ce.L = h[2];
+  ce.U = h[3];
+  ce.delta = h[4];
+  ce.cost_Z = h[5];
+  ce.n_nonfinite = (int64_t)h[7];
+  ce.gap = ce.U - ce.L;
+  ce.rel_gap = ce.U > 1e-300 ? ce.gap / ce.U : ce.gap;
+  ce.repaired_cost = repair ? h[8] : NAN;
+  if (ce.U < s->U_best) {
+    s->U_best = ce.U;
+    s->kU = ce.k;
+  }
+  if (ce.L > s->L_best) {
+    s->L_best = ce.L;
+    s->kL = ce.k;
+  }
+  ce.U_best = s->U_best;
+  ce.L_best = s->L_best;
+  ce.k_U_best = s->kU;
+  ce.k_L_best = s->kL;
+  const double g = s->U_best - s->L_best;
+  ce.rel_gap_best = s->U_best > 1e-300 ? g / s->U_best : g;
+  if (out) *out = ce;
+  if (ce.n_nonfinite > 0 || !std::isfinite(ce.L) || !std::isfinite(ce.U))
+    return fail(BDRS_E_NUMERIC, "non-finite values in the certificate at iteration %lld", (long long)ce.k);
+  return BDRS_OK;
+}
+
+bdrs_status enqueue_repair(bdrs_solver s) {
+  const LaunchCtx& c = s->ctx;
+  hipError_t e;
+  const double eps = eps_at(s, s->k - 1);
+  if ((e = launch_repair_pack(c)) != hipSuccess) return hip_status(e, "repair pack");
+  if ((e = sweep(s, false, false, s->L.splits_row, eps)) != hipSuccess) return hip_status(e, "repair sweep");
+  if ((e = launch_finish(c, false, kFinishRepair, s->L.splits_row, eps, nullptr)) != hipSuccess)
+    return hip_status(e, "repair finish");
+  if ((e = launch_repair_reduce(c)) != hipSuccess) return hip_status(e, "repair reduce");
+  if ((e = launch_prologue(c)) != hipSuccess) return hip_status(e, "prologue");  // restore cols.A
+  return BDRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bdrs_last_error(void) { return g_err.c_str(); }
+
+const char* bdrs_version(void) { return "bdrs-gfx950 0.1"; }
+
+bdrs_status bdrs_workspace_size(const bdrs_params* p, size_t* bytes) {
+  bdrs_status st = check_sizes(p);
+  if (st != BDRS_OK) return st;
+  if (!bytes) return fail(BDRS_E_INVALID, "bytes is NULL");
+  *bytes = make_layout(p->m, p->n, p->dim).total;
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_create(const bdrs_params* p, bdrs_solver* out) {
+  if (!out) return fail(BDRS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  bdrs_status st = check_params(p);
+  if (st != BDRS_OK) return st;
+  if ((st = check_device()) != BDRS_OK) return st;
+
+  const int m = p->m, n = p->n, dim = p->dim;
+  hipStream_t stream = (hipStream_t)p->stream;
+  std::vector<float> hx((size_t)m * dim), hy((size_t)n * dim);
+  std::vector<double> hr(m), hc(n);
+  HIPCHK(hipMemcpyAsync(hx.data(), p->x, hx.size() * sizeof(float), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(hy.data(), p->y, hy.size() * sizeof(float), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(hr.data(), p->r, m * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(hc.data(), p->c, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+
+  // contents: finite coordinates, strictly positive marginals of unit mass (Eq. 1)
+  for (size_t i = 0; i < hx.size(); ++i)
+    if (!std::isfinite(hx[i])) return fail(BDRS_E_INVALID, "x has a non-finite entry at %zu", i);
+  for (size_t i = 0; i < hy.size(); ++i)
+    if (!std::isfinite(hy[i])) return fail(BDRS_E_INVALID, "y has a non-finite entry at %zu", i);
+  double sr = 0, sc = 0;
+  for (int i = 0; i < m; ++i) {
+    if (!(hr[i] > 0 && std::isfinite(hr[i]))) return fail(BDRS_E_INVALID, "r[%d] is not finite and > 0", i);
+    sr += hr[i];
+  }
+  for (int j = 0; j < n; ++j) {
+    if (!(hc[j] > 0 && std::isfinite(hc[j]))) return fail(BDRS_E_INVALID, "c[%d] is not finite and > 0", j);
+    sc += hc[j];
+  }
+  if (std::fabs(sr - 1.0) > 1e-9) return fail(BDRS_E_INVALID, "r must sum to 1 (sum - 1 = %.3e)", sr - 1.0);
+  if (std::fabs(sc - 1.0) > 1e-9) return fail(BDRS_E_INVALID, "c must sum to 1 (sum - 1 = %.3e)", sc - 1.0);
+
+  bdrs_solver s = new bdrs_solver_();
+  s->prm = *p;
+  s->L = make_layout(m, n, dim);
+  fill_ctx(s);
+
+  // common origin: centre of the joint bounding box (keeps coordinates small)
+  double origin[3] = {0, 0, 0};
+  for (int d = 0; d < dim; ++d) {
+    double lo = hx[d], hi = hx[d];
+    for (int i = 0; i < m; ++i) lo = std::min(lo, (double)hx[(size_t)i * dim + d]), hi = std::max(hi, (double)hx[(size_t)i * dim + d]);
+    for (int j = 0; j < n; ++j) lo = std::min(lo, (double)hy[(size_t)j * dim + d]), hi = std::max(hi, (double)hy[(size_t)j * dim + d]);
+    origin[d] = (double)(float)(0.5 * (lo + hi));
+  }
+  HostSide R, C;
+  build_side(hx, hr, m, dim, origin, s->L.R, R);
+  build_side(hy, hc, n, dim, origin, s->L.C, C);
+
+  const LaunchCtx& c = s->ctx;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
+  };
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+  };
+  chk(up(c.rows.abs, R.abs.data(), R.abs.size() * sizeof(float)));
+  chk(up(c.rows.off, R.off.data(), R.off.size() * sizeof(float)));
+  chk(up(c.rows.hdr, R.hdr.data(), R.hdr.size() * sizeof(float)));
+  chk(up(c.rows.perm, R.perm.data(), R.perm.size() * sizeof(int)));
+  chk(up(c.rows.marg, R.marg.data(), R.marg.size() * sizeof(double)));
+  chk(up(c.rows.logmarg, R.logm.data(), R.logm.size() * sizeof(double)));
+  chk(up(c.cols.abs, C.abs.data(), C.abs.size() * sizeof(float)));
+  chk(up(c.cols.off, C.off.data(), C.off.size() * sizeof(float)));
+  chk(up(c.cols.hdr, C.hdr.data(), C.hdr.size() * sizeof(float)));
+  chk(up(c.cols.perm, C.perm.data(), C.perm.size() * sizeof(int)));
+  chk(up(c.cols.marg, C.marg.data(), C.marg.size() * sizeof(double)));
+  chk(up(c.cols.logmarg, C.logm.data(), C.logm.size() * sizeof(double)));
+  Ctrl hc0{};
+  hc0.k = 0;
+  hc0.arrive = 0;
+  hc0.eta = p->eta;
+  hc0.lam = p->lambda;
+  hc0.scale = p->cost_scale;
+  hc0.omega = p->omega;
+  chk(up(c.ctrl, &hc0, sizeof hc0));
+  // Algorithm 1 initialisation: log alpha^{-1} = log beta^{-1} = log beta^{-2} = 0
+  chk(hipMemsetAsync(c.st.la, 0, sizeof(float) * c.rows.np, stream));
+  chk(hipMemsetAsync(c.st.lah, 0, sizeof(float) * c.rows.np, stream));
+  chk(hipMemsetAsync(c.st.lb1, 0, sizeof(float) * c.cols.np, stream));
+  chk(hipMemsetAsync(c.st.lb2, 0, sizeof(float) * c.cols.np, stream));
+  chk(hipMemsetAsync(c.st.lbh, 0, sizeof(float) * c.cols.np, stream));
+  chk(hipMemsetAsync(c.st.lt[0], 0, sizeof(float) * c.cols.np, stream));
+  chk(hipMemsetAsync(c.st.lt[1], 0, sizeof(float) * c.cols.np, stream));
+  chk(hipMemsetAsync(c.cert_out, 0, sizeof(double) * kCertSlots, stream));
+  if (e == hipSuccess) e = launch_prologue(c);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    delete s;
+    return fail(BDRS_E_DEVICE, "HIP error %s while initialising the workspace", hipGetErrorString(e));
+  }
+  *out = s;
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_step(bdrs_solver s, int32_t iters) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  if (iters < 0) return fail(BDRS_E_INVALID, "iters must be >= 0");
+  for (int32_t i = 0; i < iters; ++i) {
+    bdrs_status st = enqueue_iteration(s, false);
+    if (st != BDRS_OK) return st;
+  }
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_certificate(bdrs_solver s, bdrs_cert* out) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  if (!out) return fail(BDRS_E_INVALID, "out is NULL");
+  if (s->k < 1) return fail(BDRS_E_STATE, "no iteration has run yet");
+  bdrs_status st;
+  if (!s->packed_rows && (st = repack(s)) != BDRS_OK) return st;
+  const LaunchCtx& c = s->ctx;
+  const double eps = eps_at(s, s->k - 1);
+  hipError_t e;
+  if ((e = sweep(s, true, true, s->L.splits_col, eps)) != hipSuccess) return hip_status(e, "cert sweep");
+  if ((e = launch_finish(c, true, kFinishCertOnly, s->L.splits_col, eps, nullptr)) != hipSuccess)
+    return hip_status(e, "cert finish");
+  if ((e = launch_cert_reduce(c)) != hipSuccess) return hip_status(e, "cert reduce");
+  const bool repair = (s->prm.flags & BDRS_F_REPAIR) != 0;
+  if (repair && (st = enqueue_repair(s)) != BDRS_OK) return st;
+  return read_cert(s, repair, out);
+}
+
+bdrs_status bdrs_solve(bdrs_solver s, double tau, int32_t tau_relative, int32_t max_iters, int32_t cert_every,
+                       bdrs_cert* out) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  if (!(tau >= 0 && std::isfinite(tau))) return fail(BDRS_E_INVALID, "tau must be finite and >= 0");
+  if (max_iters < 1) return fail(BDRS_E_INVALID, "max_iters must be >= 1");
+  if (cert_every < 1) return fail(BDRS_E_INVALID, "cert_every must be >= 1");
+  const bool repair = (s->prm.flags & BDRS_F_REPAIR) != 0;
+  bdrs_cert ce{};
+  bool have = false;
+  for (int32_t i = 0; i < max_iters; ++i) {
+    const long long k = s->k;
+    const bool due = ((k + 1) % cert_every == 0) || (i == max_iters - 1);
+    bdrs_status st = enqueue_iteration(s, due);
+    if (st != BDRS_OK) return st;
+    if (!due) continue;
+    hipError_t e;
+    if ((e = launch_cert_reduce(s->ctx)) != hipSuccess) return hip_status(e, "cert reduce");
+    if (repair && (st = enqueue_repair(s)) != BDRS_OK) return st;
+    st = read_cert(s, repair, &ce);
+    have = true;
+    if (st != BDRS_OK) {
+      if (out) *out = ce;
+      return st;
+    }
+    const double target = tau_relative ? ce.rel_gap_best : (ce.U_best - ce.L_best);
+    if (target <= tau) {
+      if (out) *out = ce;
+      return BDRS_OK;
+    }
+  }
+  if (out && have) *out = ce;
+  return BDRS_NOT_CONVERGED;
+}
+
+bdrs_status bdrs_get_state(bdrs_solver s, float* log_alpha, float* log_beta, float* log_beta_prev,
+                           float* log_alpha_hat, float* log_beta_hat, float* log_beta_tilde, int64_t* iters_done) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  const LaunchCtx& c = s->ctx;
+  hipError_t e = hipSuccess;
+  auto sc = [&](const float* src, const SideDev& sd, float* dst) {
+    if (dst && e == hipSuccess) e = launch_scatter(src, sd.perm, sd.count, dst, c.stream);
+  };
+  sc(c.st.la, c.rows, log_alpha);
+  sc(c.st.lb1, c.cols, log_beta);
+  sc(c.st.lb2, c.cols, log_beta_prev);
+  sc(c.st.lah, c.rows, log_alpha_hat);
+  sc(c.st.lbh, c.cols, log_beta_hat);
+  // beta-tilde used by the last finished iteration k-1 sits in buffer (k-1) & 1
+  sc(c.st.lt[(s->k + 1) & 1], c.cols, log_beta_tilde);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  if (e != hipSuccess) return hip_status(e, "get_state");
+  if (iters_done) *iters_done = s->k;
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_set_state(bdrs_solver s, const float* log_alpha, const float* log_beta, const float* log_beta_prev,
+                           const float* log_alpha_hat, const float* log_beta_hat, const float* log_beta_tilde,
+                           int64_t iters_done) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  if (!log_alpha || !log_beta || !log_beta_prev)
+    return fail(BDRS_E_INVALID, "log_alpha, log_beta and log_beta_prev are required");
+  if (iters_done < 0) return fail(BDRS_E_INVALID, "iters_done must be >= 0");
+  const LaunchCtx& c = s->ctx;
+  hipError_t e = hipSuccess;
+  auto ga = [&](const float* src, const SideDev& sd, float* dst) {
+    if (src && e == hipSuccess) e = launch_gather(src, sd.perm, sd.np, dst, c.stream);
+  };
+  ga(log_alpha, c.rows, c.st.la);
+  ga(log_beta, c.cols, c.st.lb1);
+  ga(log_beta_prev, c.cols, c.st.lb2);
+  ga(log_alpha_hat, c.rows, c.st.lah);
+  ga(log_beta_hat, c.cols, c.st.lbh);
+  ga(log_beta_tilde, c.cols, c.st.lt[(iters_done + 1) & 1]);
+  if (e != hipSuccess) return hip_status(e, "set_state");
+  long long k = iters_done;
+  HIPCHK(hipMemcpyAsync(&c.ctrl->k, &k, sizeof k, hipMemcpyHostToDevice, c.stream));
+  s->k = k;
+  s->U_best = INFINITY;
+  s->L_best = -INFINITY;
+  s->kU = s->kL = -1;
+  s->packed_rows = false;
+  bdrs_status st = BDRS_OK;
+  if (log_alpha_hat) st = repack(s);
+  else {
+    hipError_t e2 = launch_prologue(c);
+    if (e2 != hipSuccess) st = hip_status(e2, "prologue");
+  }
+  if (st != BDRS_OK) return st;
+  HIPCHK(hipStreamSynchronize(c.stream));
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_lse(bdrs_solver s, int32_t transpose, double eps, const float* w, float* out) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  if (!w || !out) return fail(BDRS_E_INVALID, "w and out are required");
+  if (!(eps > 0 && std::isfinite(eps))) return fail(BDRS_E_INVALID, "eps must be finite and > 0");
+  const LaunchCtx& c = s->ctx;
+  const bool tr = transpose != 0;
+  const int splits = tr ? s->L.splits_col : s->L.splits_row;
+  hipError_t e;
+  if ((e = launch_pack(c, tr, w, eps)) != hipSuccess) return hip_status(e, "pack");
+  if ((e = sweep(s, tr, false, splits, eps)) != hipSuccess) return hip_status(e, "sweep");
+  if ((e = launch_finish(c, tr, kFinishLse, splits, eps, out)) != hipSuccess) return hip_status(e, "finish");
+  s->packed_rows = false;
+  return repack(s);
+}
+
+bdrs_status bdrs_profile(bdrs_solver s, int32_t enable) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  HIPCHK(hipStreamSynchronize(s->ctx.stream));
+  s->prof = enable != 0;
+  if (s->prof) {
+    s->ev_used = 0;
+    s->prof_entries = 0.0;
+    s->prof_sweeps = 0;
+  }
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_profile_read(bdrs_solver s, int64_t* sweeps, double* ms, double* entries) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  HIPCHK(hipStreamSynchronize(s->ctx.stream));
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < s->ev_used; i += 2) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, s->ev_pool[i], s->ev_pool[i + 1]));
+    tot += t;
+  }
+  if (sweeps) *sweeps = s->prof_sweeps;
+  if (ms) *ms = tot;
+  if (entries) *entries = s->prof_entries;
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_destroy(bdrs_solver s) {
+  if (!s) return BDRS_OK;
+  hipError_t e = hipStreamSynchronize(s->ctx.stream);
+  for (hipEvent_t ev : s->ev_pool) hipEventDestroy(ev);
+  delete s;
+  if (e != hipSuccess) return hip_status(e, "destroy");
+  return BDRS_OK;
+}
+
+}  // extern "C"

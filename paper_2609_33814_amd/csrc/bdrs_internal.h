@@ -1,0 +1,96 @@
+// Internal declarations shared by the kernels and the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bdrs {
+
+constexpr int kTile = 64;         // points per tile = one wavefront
+constexpr int kBlock = 256;       // threads per block in every kernel
+constexpr int kHdr = 8;           // floats per tile header: center[3], radius[3], pad[2]
+constexpr int kCertSlots = 16;    // doubles in a certificate record
+
+// Device-resident control block of one solver: the iteration counter lives
+// here so that a captured block of iterations can be replayed at any k.
+struct Ctrl {
+  long long k;             // index of the next iteration of Algorithm 1
+  unsigned int arrive;     // last-block-done counter of the column epilogue
+  unsigned int pad0;
+  double eta, lam, scale;  // eta, lambda, cost scale s
+  double omega;
+};
+
+// One point set stored in tile order.  Slot p holds original point perm[p];
+// slots >= count are padding (copies of a real point with weight -inf).
+struct SideDev {
+  int count;       // real points
+  int ntiles;      // ceil(count / 64)
+  int np;          // ntiles * 64, padded to a multiple of 256 for the epilogues
+  int pad;
+  float* abs;      // [dim][np] coordinates relative to the common origin (SoA)
+  float* off;      // [ntiles][dim][64] offsets from the tile centre
+  float* hdr;      // [ntiles][8] centre[3], per-dimension radius[3]
+  float* A;        // [np] packed log2 weights of the next sweep that reads this side
+  float* Amax;     // [ntiles] tile maxima of A
+  int* perm;       // [np] original index of each slot
+  double* marg;    // [np] marginal (r or c), 0 on padding
+  double* logmarg; // [np] log marginal
+};
+
+// Dual state (float32, tile order).
+struct StateDev {
+  float* la;        // log alpha^{k-1}  (rows)
+  float* lah;       // log alpha-hat    (rows)
+  float* lb1;       // log beta^{k-1}   (cols)
+  float* lb2;       // log beta^{k-2}   (cols)
+  float* lbh;       // log beta-hat     (cols)
+  float* lt[2];     // log beta-tilde, ping-pong by parity of k (cols)
+  double* mu;       // certificate: mean column cost mu_j
+  double* logs;     // certificate: log s_j
+  double* pvec;     // repair: row deficits p_i
+};
+
+struct Partials {
+  float* M;   // [S][np] running max (log2)
+  float* S;   // [S][np] shifted sum
+  float* N;   // [S][np] shifted cost-weighted sum (certificate sweeps)
+  int splits; // allocated splits
+};
+
+enum FinishKind {
+  kFinishRow = 0,       // Algorithm 1 row epilogue
+  kFinishCol = 1,       // Algorithm 1 column epilogue (advances k)
+  kFinishColCert = 2,   // column epilogue + Algorithm 2 column statistics
+  kFinishLse = 3,       // plain LSE output (parity entry point)
+  kFinishRepair = 4,    // repair deficits p_i
+  kFinishCertOnly = 5   // Algorithm 2 column statistics of the last finished iteration
+};
+
+struct LaunchCtx {
+  hipStream_t stream;
+  int dim;
+  Ctrl* ctrl;
+  SideDev rows, cols;
+  StateDev st;
+  Partials part;
+  double* cert_part;   // [cert_blocks][8]
+  double* cert_out;    // [kCertSlots]
+  int cert_blocks;
+};
+
+// Kernel launchers (bdrs_kernels.hip).  Each returns the launch status.
+hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int splits, double eps_arg);
+hipError_t launch_finish(const LaunchCtx& c, bool transpose, FinishKind kind, int splits,
+                         double eps_arg, float* lse_out);
+hipError_t launch_prologue(const LaunchCtx& c);                       // lt and A_C for iteration k
+hipError_t launch_pack(const LaunchCtx& c, bool transpose, const float* w, double eps);
+hipError_t launch_pack_rows_from_lah(const LaunchCtx& c, double eps);
+hipError_t launch_cert_reduce(const LaunchCtx& c);
+hipError_t launch_repair_pack(const LaunchCtx& c);
+hipError_t launch_repair_reduce(const LaunchCtx& c);
+hipError_t launch_scatter(const float* src, const int* perm, int count, float* dst, hipStream_t s);
+hipError_t launch_gather(const float* src, const int* perm, int np, float* dst, hipStream_t s);
+
+int choose_splits(int np_out, int ntiles_in);
+
+}  // namespace bdrs

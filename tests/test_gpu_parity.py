@@ -1,0 +1,258 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (written here, derived in the design notes):
+* one LSE sweep: ||y_gpu - y_ref||_inf / max(1, ||y_ref||_inf) <= 1e-5, both
+  sides fed the same float32 inputs, y_ref in float64;
+* the 500-iteration 32x32 trajectory: relative gap at the last certificate
+  within 1e-3 relative of the oracle's own trajectory;
+* a certificate evaluated from an identical state: L and U within 1e-6
+  relative (float32 sweep, float64 sums).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import alg1, certificate, lp, lse, repair  # noqa: E402
+from paper_2609_33814_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+SWEEP_TOL = 1e-5
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def solver_for(prob, eta=1.0, lam=1.0, repair_flag=False):
+    from paper_2609_33814_amd import bdrs
+    d = dev()
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=d)
+    return bdrs.Solver(t(prob.x, torch.float32), t(prob.y, torch.float32),
+                       t(prob.r, torch.float64), t(prob.c, torch.float64),
+                       prob.cost_scale, eta=eta, lam=lam, repair=repair_flag)
+
+
+def rel_err(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.max(np.abs(got - ref)) / max(1.0, float(np.max(np.abs(ref)))))
+
+
+def sweep_both(sv, prob, w32, eps, transpose):
+    """GPU sweep and the oracle's on identical float32 inputs."""
+    got = sv.lse(torch.as_tensor(w32, device=dev()), eps, transpose=transpose).cpu().numpy()
+    if transpose:
+        ref = lse.implicit_lse(prob.y, prob.x, prob.cost_scale, eps, w32.astype(np.float64))
+    else:
+        ref = lse.implicit_lse(prob.x, prob.y, prob.cost_scale, eps, w32.astype(np.float64))
+    return got, ref
+
+
+# ----------------------------------------------------------------------------
+# single sweeps
+# ----------------------------------------------------------------------------
+SHAPES = [
+    ("grid32", lambda: inputs.c1_problem()),
+    ("rand_ragged_d3", lambda: inputs.random_problem(300, 517, 3, 1)),
+    ("rand_d1", lambda: inputs.random_problem(77, 1000, 1, 2)),
+    ("rand_d2_tall", lambda: inputs.random_problem(1000, 65, 2, 3)),
+    ("single", lambda: inputs.random_problem(1, 1, 2, 4)),
+    ("one_row", lambda: inputs.random_problem(1, 700, 3, 5)),
+    ("colour", lambda: inputs.colour_problem(2000, 1500, 31, 32)),
+    ("grid_int_coords", lambda: inputs.random_problem(200, 333, 2, 6, integer=True, span=40)),
+]
+
+
+@pytest.mark.parametrize("name,make", SHAPES, ids=[s[0] for s in SHAPES])
+@pytest.mark.parametrize("eps", [1.0, 0.03, 1e-3])
+def test_sweep_parity_random_weights(name, make, eps):
+    prob = make()
+    sv = solver_for(prob)
+    rng = np.random.default_rng(17)
+    for transpose in (False, True):
+        n_in = prob.m if transpose else prob.n
+        w = rng.normal(0.0, 20.0, n_in).astype(np.float32)
+        got, ref = sweep_both(sv, prob, w, eps, transpose)
+        assert rel_err(got, ref) <= SWEEP_TOL, (name, eps, transpose, rel_err(got, ref))
+
+
+def test_sweep_duplicate_points_and_masked_weights():
+    rng = np.random.default_rng(3)
+    x = np.repeat(rng.random((10, 2)).astype(np.float32), 13, axis=0)   # 130 points, 10 distinct
+    y = np.zeros((200, 2), dtype=np.float32)                            # all targets identical
+    r = np.full(130, 1 / 130)
+    c = np.full(200, 1 / 200)
+    prob = inputs.Problem(x=x, y=y, r=r, c=c, cost_scale=1.0)
+    sv = solver_for(prob)
+    w = rng.normal(0, 5, 200).astype(np.float32)
+    w[::3] = -np.inf                                                    # masked columns
+    got, ref = sweep_both(sv, prob, w, 0.01, False)
+    assert rel_err(got, ref) <= SWEEP_TOL
+    w_all = np.full(200, -np.inf, dtype=np.float32)                     # empty sum -> -inf
+    got = sv.lse(torch.as_tensor(w_all, device=dev()), 0.01).cpu().numpy()
+    assert np.all(got == -np.inf)
+
+
+# ----------------------------------------------------------------------------
+# the 32x32 workload: 500 iterations, certificate every 50
+# ----------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c1_oracle():
+    prob = inputs.c1_problem()
+    st, certs, states = alg1.run(prob, 1.0, 1.0, 500, cert_every=50, keep_states=True)
+    return prob, st, certs, states
+
+
+@pytest.mark.parametrize("k", [0, 1, 10, 100, 499])
+def test_c1_sweep_parity_on_trajectory_states(c1_oracle, k):
+    """Row and column sweeps of iteration k, fed the oracle's own state (float32)."""
+    prob, _, _, states = c1_oracle
+    st = states[k]
+    eps = alg1.schedule(1.0, 1.0, k)
+    sv = solver_for(prob)
+    got, ref = sweep_both(sv, prob, st.lt.astype(np.float32), eps, False)
+    assert rel_err(got, ref) <= SWEEP_TOL, rel_err(got, ref)
+    got, ref = sweep_both(sv, prob, st.lah.astype(np.float32), eps, True)
+    assert rel_err(got, ref) <= SWEEP_TOL, rel_err(got, ref)
+
+
+def test_c1_trajectory_parity(c1_oracle):
+    prob, st_ref, certs_ref, _ = c1_oracle
+    sv = solver_for(prob)
+    ok, ce = sv.solve(0.0, 500, 50)
+    assert not ok and ce["k"] == 499
+    ref = certs_ref[-1]
+    assert ref["k"] == 499
+    rel_ref = ref["rel"]
+    assert abs(ce["rel_gap"] - rel_ref) / rel_ref <= 1e-3, (ce["rel_gap"], rel_ref)
+    assert abs(ce["U"] - ref["U"]) / ref["U"] <= 1e-4
+    assert abs(ce["L"] - ref["L"]) / abs(ref["L"]) <= 1e-4
+    # potentials f = eps log A, g = eps log(B / c)
+    gs = sv.get_state()
+    eps = ref["eps"]
+    f_gpu = eps * gs["lah"].cpu().numpy().astype(np.float64)
+    g_gpu = eps * (gs["lbh"].cpu().numpy().astype(np.float64) - np.log(prob.c))
+    assert rel_err(f_gpu, ref["f"]) <= 1e-4
+    assert rel_err(g_gpu, ref["g"]) <= 1e-4
+    assert gs["k"] == 500
+
+
+def test_certificate_from_identical_state(c1_oracle):
+    prob, _, _, states = c1_oracle
+    k = 199
+    st = states[k]
+    r32 = lambda a: a.astype(np.float32)
+    d = dev()
+    sv = solver_for(prob)
+    sv.set_state(dict(la=torch.as_tensor(r32(st.la), device=d), lb=torch.as_tensor(r32(st.lb1), device=d),
+                      lb_prev=torch.as_tensor(r32(st.lb2), device=d), lah=torch.as_tensor(r32(st.lah), device=d),
+                      lbh=torch.as_tensor(r32(st.lbh), device=d), lt=torch.as_tensor(r32(st.lt), device=d),
+                      k=k + 1))
+    ce = sv.certificate()
+    eps = alg1.schedule(1.0, 1.0, k)
+    ref = certificate.certificate(prob.x, prob.y, prob.cost_scale, prob.r, prob.c,
+                                  r32(st.lah).astype(np.float64), r32(st.lbh).astype(np.float64),
+                                  r32(st.lt).astype(np.float64), eps)
+    assert ce["k"] == k
+    assert abs(ce["L"] - ref["L"]) <= 1e-6 * abs(ref["L"])
+    assert abs(ce["U"] - ref["U"]) <= 1e-6 * abs(ref["U"])
+    assert abs(ce["delta"] - ref["delta"]) <= 1e-4 * ref["delta"] + 1e-9
+    assert ce["n_nonfinite"] == 0
+
+
+# ----------------------------------------------------------------------------
+# overrelaxation, resume, repair, exact optimum
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("lam", [1.5, 1.99])
+def test_obdrs_trajectory_parity(lam):
+    prob = inputs.grid_problem(16, 7, 8)
+    _, certs, _ = alg1.run(prob, 1.0, lam, 200, cert_every=50)
+    sv = solver_for(prob, lam=lam)
+    ok, ce = sv.solve(0.0, 200, 50)
+    ref = certs[-1]
+    assert ce["k"] == ref["k"] == 199
+    assert abs(ce["rel_gap"] - ref["rel"]) / ref["rel"] <= 1e-3
+    assert abs(ce["U"] - ref["U"]) / ref["U"] <= 1e-4
+
+
+def test_resume_is_bitwise():
+    prob = inputs.grid_problem(24, 1, 2)
+    a = solver_for(prob)
+    a.step(100)
+    sa = a.get_state()
+    b = solver_for(prob)
+    b.step(50)
+    mid = b.get_state()
+    c = solver_for(prob)
+    c.set_state(mid)
+    c.step(50)
+    sc = c.get_state()
+    for key in ("la", "lb", "lb_prev", "lah", "lbh", "lt"):
+        assert torch.equal(sa[key], sc[key]), key
+    assert sa["k"] == sc["k"] == 100
+
+
+def test_repeat_runs_are_bitwise_equal():
+    prob = inputs.random_problem(500, 700, 3, 9)
+    outs = []
+    for _ in range(2):
+        sv = solver_for(prob, eta=0.3)
+        sv.step(30)
+        outs.append(sv.get_state())
+    for key in ("la", "lb", "lah"):
+        assert torch.equal(outs[0][key], outs[1][key])
+
+
+@pytest.mark.parametrize("lam", [1.0, 1.99])
+def test_repaired_cost_parity_and_bracket(lam):
+    prob = inputs.random_problem(40, 50, 2, 12)
+    C = lse.cost_matrix(prob.x, prob.y, prob.cost_scale)
+    pstar = lp.linprog_ot(C, prob.r, prob.c)
+    sv = solver_for(prob, eta=0.5, lam=lam, repair_flag=True)
+    sv.step(60)
+    ce = sv.certificate()
+    gs = sv.get_state()
+    eps = alg1.schedule(0.5, lam, 59)
+    lah = gs["lah"].cpu().numpy().astype(np.float64)
+    lt = gs["lt"].cpu().numpy().astype(np.float64)
+    lbh = gs["lbh"].cpu().numpy().astype(np.float64)
+    ref = certificate.certificate(prob.x, prob.y, prob.cost_scale, prob.r, prob.c, lah, lbh, lt, eps)
+    rp = repair.dense_repair(prob.x, prob.y, prob.cost_scale, prob.r, prob.c, lah, lt, eps)
+    assert abs(ce["repaired_cost"] - rp["cost_Zhat"]) <= 1e-6 * rp["cost_Zhat"]
+    assert ce["L"] <= pstar + 1e-7 and pstar <= ce["repaired_cost"] + 1e-7
+    assert ce["repaired_cost"] <= ce["U"] + 1e-7
+    assert abs(ce["U"] - ref["U"]) <= 1e-6 * ref["U"]
+
+
+def test_bracket_exact_1d_optimum_large():
+    rng = np.random.default_rng(5)
+    m, n = 20000, 15000
+    x = rng.random((m, 1)).astype(np.float32)
+    y = (rng.random((n, 1)) ** 2).astype(np.float32)
+    r = rng.uniform(0.5, 1.5, m); r /= r.sum()
+    c = rng.uniform(0.5, 1.5, n); c /= c.sum()
+    prob = inputs.Problem(x=x, y=y, r=r, c=c, cost_scale=1.0)
+    pstar = lp.sorted_1d(x, y, r, c, 1.0)
+    sv = solver_for(prob, eta=0.1)
+    ok, ce = sv.solve(0.0, 300, 100)
+    assert ce["L_best"] <= pstar + 1e-6 * pstar
+    assert pstar <= ce["U_best"] + 1e-6 * pstar
+    assert ce["rel_gap_best"] < 0.5
+
+
+def test_full_size_grid_sampled_rows():
+    """128x128 grids (16384 points per side) at the benchmark's launch shape;
+    sampled output rows checked one by one against the oracle."""
+    prob = inputs.c2_problem()
+    sv = solver_for(prob)
+    rng = np.random.default_rng(23)
+    rows = rng.choice(prob.m, 256, replace=False)
+    for eps in (1.0, 2e-3):
+        w = rng.normal(0, 30, prob.n).astype(np.float32)
+        got = sv.lse(torch.as_tensor(w, device=dev()), eps).cpu().numpy()[rows]
+        ref = lse.implicit_lse(prob.x, prob.y, prob.cost_scale, eps, w.astype(np.float64), rows=rows)
+        assert rel_err(got, ref) <= SWEEP_TOL
