@@ -145,35 +145,37 @@ BDRS_API bdrs_status bdrs_certificate(bdrs_solver s, bdrs_cert *out);
 BDRS_API bdrs_status bdrs_solve(bdrs_solver s, double tau, int32_t tau_relative,
                        int32_t max_iters, int32_t cert_every, bdrs_cert *out);
 
-/* Copies the dual state of Algorithm 1 into caller device buffers (float32,
+/* Copies the dual state of Algorithm 1 into caller device buffers (float64,
  * original point order; NULL skips a vector): log alpha^k (m), log beta^k
  * (n), log beta^{k-1} (n), log alpha-hat^k (m), log beta-hat^k (n),
  * log beta-tilde^{k-1} (n), and the number of finished iterations (host).
- * Synchronous. */
-BDRS_API bdrs_status bdrs_get_state(bdrs_solver s, float *log_alpha, float *log_beta,
-                           float *log_beta_prev, float *log_alpha_hat,
-                           float *log_beta_hat, float *log_beta_tilde,
+ * The state is held in float64 (O(m + n)); only the O(m n) sweeps run in
+ * float32.  Synchronous. */
+BDRS_API bdrs_status bdrs_get_state(bdrs_solver s, double *log_alpha, double *log_beta,
+                           double *log_beta_prev, double *log_alpha_hat,
+                           double *log_beta_hat, double *log_beta_tilde,
                            int64_t *iters_done);
 
-/* Replaces the dual state (device float32 buffers in original point order;
+/* Replaces the dual state (device float64 buffers in original point order;
  * log_alpha, log_beta and log_beta_prev are required, the hats and
  * beta-tilde are optional) and the iteration counter; resuming from a state
  * saved by bdrs_get_state continues the same trajectory.  Resets the best
  * bounds.  Synchronous. */
-BDRS_API bdrs_status bdrs_set_state(bdrs_solver s, const float *log_alpha,
-                           const float *log_beta, const float *log_beta_prev,
-                           const float *log_alpha_hat, const float *log_beta_hat,
-                           const float *log_beta_tilde, int64_t iters_done);
+BDRS_API bdrs_status bdrs_set_state(bdrs_solver s, const double *log_alpha,
+                           const double *log_beta, const double *log_beta_prev,
+                           const double *log_alpha_hat, const double *log_beta_hat,
+                           const double *log_beta_tilde, int64_t iters_done);
 
 /* One LSE sweep on the solver's problem, for parity checks of the kernel:
  * out_i = LSE_j( w_j - C_ij / eps ) in natural-log units (the reduction of
  * the row update of Algorithm 1) when transpose == 0, and
  * out_j = LSE_i( w_i - C_ij / eps ) (the column update) when transpose != 0.
- * w and out are device float32 in original point order (length n / m resp.
- * m / n).  Uses the solver's workspace (clobbers its sweep buffers but not
+ * w and out are device float64 in original point order (length n / m resp.
+ * m / n); the sweep itself runs in float32 on weights taken relative to
+ * their tile maximum.  Uses the solver's workspace (clobbers its sweep buffers but not
  * the dual state).  Asynchronous. */
 BDRS_API bdrs_status bdrs_lse(bdrs_solver s, int32_t transpose, double eps,
-                     const float *w, float *out);
+                     const double *w, double *out);
 
 /* Kernel timing for measurement.  enable != 0 brackets every LSE sweep
  * kernel this solver launches from then on with a pair of HIP events on the

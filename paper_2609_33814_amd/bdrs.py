@@ -166,24 +166,24 @@ class Solver:
     def get_state(self) -> dict:
         torch = self._torch
         dev = self._inputs[0].device
-        la = torch.empty(self.m, dtype=torch.float32, device=dev)
+        la = torch.empty(self.m, dtype=torch.float64, device=dev)
         lah = torch.empty_like(la)
-        lb, lb1, lbh, lt = (torch.empty(self.n, dtype=torch.float32, device=dev) for _ in range(4))
+        lb, lb1, lbh, lt = (torch.empty(self.n, dtype=torch.float64, device=dev) for _ in range(4))
         k = ctypes.c_int64()
         check(lib().bdrs_get_state(self._h, _ptr(la), _ptr(lb), _ptr(lb1), _ptr(lah), _ptr(lbh),
                                    _ptr(lt), ctypes.byref(k)))
         return dict(la=la, lb=lb, lb_prev=lb1, lah=lah, lbh=lbh, lt=lt, k=k.value)
 
     def set_state(self, st: dict) -> None:
-        f = lambda key: None if st.get(key) is None else st[key].contiguous()
+        f = lambda key: None if st.get(key) is None else st[key].to(self._torch.float64).contiguous()
         keep = [f(key) for key in ("la", "lb", "lb_prev", "lah", "lbh", "lt")]
         check(lib().bdrs_set_state(self._h, *[_ptr(t) for t in keep], int(st["k"])))
 
     def lse(self, w, eps: float, transpose: bool = False):
-        """out_i = LSE_j(w_j - C_ij/eps) (or the transposed reduction), float32."""
+        """out_i = LSE_j(w_j - C_ij/eps) (or the transposed reduction); float64 in and out."""
         torch = self._torch
-        w = w.contiguous()
-        out = torch.empty(self.n if transpose else self.m, dtype=torch.float32, device=w.device)
+        w = w.to(torch.float64).contiguous()
+        out = torch.empty(self.n if transpose else self.m, dtype=torch.float64, device=w.device)
         check(lib().bdrs_lse(self._h, 1 if transpose else 0, float(eps), _ptr(w), _ptr(out)))
         return out
 

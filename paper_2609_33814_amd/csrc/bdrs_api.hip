@@ -91,25 +91,25 @@ Layout make_layout(int m, int n, int dim) {
     off = take(sizeof(float) * (size_t)s.ntiles * dim * kTile);
     hdr = take(sizeof(float) * (size_t)s.ntiles * kHdr);
     A = take(sizeof(float) * (size_t)s.np);
-    Amax = take(sizeof(float) * (size_t)s.ntiles);
+    Amax = take(sizeof(double) * (size_t)s.ntiles);
     perm = take(sizeof(int) * (size_t)s.np);
     marg = take(sizeof(double) * (size_t)s.np);
     logm = take(sizeof(double) * (size_t)s.np);
   };
   side(L.R, L.r_abs, L.r_off, L.r_hdr, L.r_A, L.r_Amax, L.r_perm, L.r_marg, L.r_logm);
   side(L.C, L.c_abs, L.c_off, L.c_hdr, L.c_A, L.c_Amax, L.c_perm, L.c_marg, L.c_logm);
-  L.la = take(sizeof(float) * L.R.np);
-  L.lah = take(sizeof(float) * L.R.np);
-  L.lb1 = take(sizeof(float) * L.C.np);
-  L.lb2 = take(sizeof(float) * L.C.np);
-  L.lbh = take(sizeof(float) * L.C.np);
-  L.lt0 = take(sizeof(float) * L.C.np);
-  L.lt1 = take(sizeof(float) * L.C.np);
+  L.la = take(sizeof(double) * L.R.np);
+  L.lah = take(sizeof(double) * L.R.np);
+  L.lb1 = take(sizeof(double) * L.C.np);
+  L.lb2 = take(sizeof(double) * L.C.np);
+  L.lbh = take(sizeof(double) * L.C.np);
+  L.lt0 = take(sizeof(double) * L.C.np);
+  L.lt1 = take(sizeof(double) * L.C.np);
   L.mu = take(sizeof(double) * L.C.np);
   L.logs = take(sizeof(double) * L.C.np);
   L.pvec = take(sizeof(double) * L.R.np);
   const size_t pelems = (size_t)std::max((size_t)L.splits_row * L.R.np, (size_t)L.splits_col * L.C.np);
-  L.pM = take(sizeof(float) * pelems);
+  L.pM = take(sizeof(double) * pelems);
   L.pS = take(sizeof(float) * pelems);
   L.pN = take(sizeof(float) * pelems);
   L.cert_part = take(sizeof(double) * 2 * (size_t)L.cert_blocks * 8);
@@ -286,24 +286,24 @@ void fill_ctx(bdrs_solver s) {
     sd.off = (float*)(base + off);
     sd.hdr = (float*)(base + hdr);
     sd.A = (float*)(base + A);
-    sd.Amax = (float*)(base + Amax);
+    sd.Amax = (double*)(base + Amax);
     sd.perm = (int*)(base + perm);
     sd.marg = (double*)(base + marg);
     sd.logmarg = (double*)(base + logm);
   };
   side(c.rows, L.R, L.r_abs, L.r_off, L.r_hdr, L.r_A, L.r_Amax, L.r_perm, L.r_marg, L.r_logm);
   side(c.cols, L.C, L.c_abs, L.c_off, L.c_hdr, L.c_A, L.c_Amax, L.c_perm, L.c_marg, L.c_logm);
-  c.st.la = (float*)(base + L.la);
-  c.st.lah = (float*)(base + L.lah);
-  c.st.lb1 = (float*)(base + L.lb1);
-  c.st.lb2 = (float*)(base + L.lb2);
-  c.st.lbh = (float*)(base + L.lbh);
-  c.st.lt[0] = (float*)(base + L.lt0);
-  c.st.lt[1] = (float*)(base + L.lt1);
+  c.st.la = (double*)(base + L.la);
+  c.st.lah = (double*)(base + L.lah);
+  c.st.lb1 = (double*)(base + L.lb1);
+  c.st.lb2 = (double*)(base + L.lb2);
+  c.st.lbh = (double*)(base + L.lbh);
+  c.st.lt[0] = (double*)(base + L.lt0);
+  c.st.lt[1] = (double*)(base + L.lt1);
   c.st.mu = (double*)(base + L.mu);
   c.st.logs = (double*)(base + L.logs);
   c.st.pvec = (double*)(base + L.pvec);
-  c.part.M = (float*)(base + L.pM);
+  c.part.M = (double*)(base + L.pM);
   c.part.S = (float*)(base + L.pS);
   c.part.N = (float*)(base + L.pN);
   c.part.splits = L.splits_max;
@@ -512,13 +512,13 @@ bdrs_status bdrs_create(const bdrs_params* p, bdrs_solver* out) {
   hc0.omega = p->omega;
   chk(up(c.ctrl, &hc0, sizeof hc0));
   // Algorithm 1 initialisation: log alpha^{-1} = log beta^{-1} = log beta^{-2} = 0
-  chk(hipMemsetAsync(c.st.la, 0, sizeof(float) * c.rows.np, stream));
-  chk(hipMemsetAsync(c.st.lah, 0, sizeof(float) * c.rows.np, stream));
-  chk(hipMemsetAsync(c.st.lb1, 0, sizeof(float) * c.cols.np, stream));
-  chk(hipMemsetAsync(c.st.lb2, 0, sizeof(float) * c.cols.np, stream));
-  chk(hipMemsetAsync(c.st.lbh, 0, sizeof(float) * c.cols.np, stream));
-  chk(hipMemsetAsync(c.st.lt[0], 0, sizeof(float) * c.cols.np, stream));
-  chk(hipMemsetAsync(c.st.lt[1], 0, sizeof(float) * c.cols.np, stream));
+  chk(hipMemsetAsync(c.st.la, 0, sizeof(double) * c.rows.np, stream));
+  chk(hipMemsetAsync(c.st.lah, 0, sizeof(double) * c.rows.np, stream));
+  chk(hipMemsetAsync(c.st.lb1, 0, sizeof(double) * c.cols.np, stream));
+  chk(hipMemsetAsync(c.st.lb2, 0, sizeof(double) * c.cols.np, stream));
+  chk(hipMemsetAsync(c.st.lbh, 0, sizeof(double) * c.cols.np, stream));
+  chk(hipMemsetAsync(c.st.lt[0], 0, sizeof(double) * c.cols.np, stream));
+  chk(hipMemsetAsync(c.st.lt[1], 0, sizeof(double) * c.cols.np, stream));
   chk(hipMemsetAsync(c.cert_out, 0, sizeof(double) * kCertSlots, stream));
   if (e == hipSuccess) e = launch_prologue(c);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -592,12 +592,12 @@ bdrs_status bdrs_solve(bdrs_solver s, double tau, int32_t tau_relative, int32_t 
   return BDRS_NOT_CONVERGED;
 }
 
-bdrs_status bdrs_get_state(bdrs_solver s, float* log_alpha, float* log_beta, float* log_beta_prev,
-                           float* log_alpha_hat, float* log_beta_hat, float* log_beta_tilde, int64_t* iters_done) {
+bdrs_status bdrs_get_state(bdrs_solver s, double* log_alpha, double* log_beta, double* log_beta_prev,
+                           double* log_alpha_hat, double* log_beta_hat, double* log_beta_tilde, int64_t* iters_done) {
   if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
   const LaunchCtx& c = s->ctx;
   hipError_t e = hipSuccess;
-  auto sc = [&](const float* src, const SideDev& sd, float* dst) {
+  auto sc = [&](const double* src, const SideDev& sd, double* dst) {
     if (dst && e == hipSuccess) e = launch_scatter(src, sd.perm, sd.count, dst, c.stream);
   };
   sc(c.st.la, c.rows, log_alpha);
@@ -613,16 +613,16 @@ bdrs_status bdrs_get_state(bdrs_solver s, float* log_alpha, float* log_beta, flo
   return BDRS_OK;
 }
 
-bdrs_status bdrs_set_state(bdrs_solver s, const float* log_alpha, const float* log_beta, const float* log_beta_prev,
-                           const float* log_alpha_hat, const float* log_beta_hat, const float* log_beta_tilde,
-                           int64_t iters_done) {
+bdrs_status bdrs_set_state(bdrs_solver s, const double* log_alpha, const double* log_beta,
+                           const double* log_beta_prev, const double* log_alpha_hat, const double* log_beta_hat,
+                           const double* log_beta_tilde, int64_t iters_done) {
   if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
   if (!log_alpha || !log_beta || !log_beta_prev)
     return fail(BDRS_E_INVALID, "log_alpha, log_beta and log_beta_prev are required");
   if (iters_done < 0) return fail(BDRS_E_INVALID, "iters_done must be >= 0");
   const LaunchCtx& c = s->ctx;
   hipError_t e = hipSuccess;
-  auto ga = [&](const float* src, const SideDev& sd, float* dst) {
+  auto ga = [&](const double* src, const SideDev& sd, double* dst) {
     if (src && e == hipSuccess) e = launch_gather(src, sd.perm, sd.np, dst, c.stream);
   };
   ga(log_alpha, c.rows, c.st.la);
@@ -650,7 +650,7 @@ bdrs_status bdrs_set_state(bdrs_solver s, const float* log_alpha, const float* l
   return BDRS_OK;
 }
 
-bdrs_status bdrs_lse(bdrs_solver s, int32_t transpose, double eps, const float* w, float* out) {
+bdrs_status bdrs_lse(bdrs_solver s, int32_t transpose, double eps, const double* w, double* out) {
   if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
   if (!w || !out) return fail(BDRS_E_INVALID, "w and out are required");
   if (!(eps > 0 && std::isfinite(eps))) return fail(BDRS_E_INVALID, "eps must be finite and > 0");

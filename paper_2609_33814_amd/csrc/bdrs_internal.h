@@ -30,28 +30,29 @@ struct SideDev {
   float* abs;      // [dim][np] coordinates relative to the common origin (SoA)
   float* off;      // [ntiles][dim][64] offsets from the tile centre
   float* hdr;      // [ntiles][8] centre[3], per-dimension radius[3]
-  float* A;        // [np] packed log2 weights of the next sweep that reads this side
-  float* Amax;     // [ntiles] tile maxima of A
+  float* A;        // [np] log2 weights of the next sweep that reads this side, relative
+                   //      to their tile maximum (small magnitudes, float32)
+  double* Amax;    // [ntiles] tile maxima of the absolute log2 weights (float64)
   int* perm;       // [np] original index of each slot
   double* marg;    // [np] marginal (r or c), 0 on padding
   double* logmarg; // [np] log marginal
 };
 
-// Dual state (float32, tile order).
+// Dual state (float64, tile order; O(m + n)).
 struct StateDev {
-  float* la;        // log alpha^{k-1}  (rows)
-  float* lah;       // log alpha-hat    (rows)
-  float* lb1;       // log beta^{k-1}   (cols)
-  float* lb2;       // log beta^{k-2}   (cols)
-  float* lbh;       // log beta-hat     (cols)
-  float* lt[2];     // log beta-tilde, ping-pong by parity of k (cols)
+  double* la;       // log alpha^{k-1}  (rows)
+  double* lah;      // log alpha-hat    (rows)
+  double* lb1;      // log beta^{k-1}   (cols)
+  double* lb2;      // log beta^{k-2}   (cols)
+  double* lbh;      // log beta-hat     (cols)
+  double* lt[2];    // log beta-tilde, ping-pong by parity of k (cols)
   double* mu;       // certificate: mean column cost mu_j
   double* logs;     // certificate: log s_j
   double* pvec;     // repair: row deficits p_i
 };
 
 struct Partials {
-  float* M;   // [S][np] running max (log2)
+  double* M;  // [S][np] running shift (log2, float64)
   float* S;   // [S][np] shifted sum
   float* N;   // [S][np] shifted cost-weighted sum (certificate sweeps)
   int splits; // allocated splits
@@ -81,15 +82,15 @@ struct LaunchCtx {
 // Kernel launchers (bdrs_kernels.hip).  Each returns the launch status.
 hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int splits, double eps_arg);
 hipError_t launch_finish(const LaunchCtx& c, bool transpose, FinishKind kind, int splits,
-                         double eps_arg, float* lse_out);
+                         double eps_arg, double* lse_out);
 hipError_t launch_prologue(const LaunchCtx& c);                       // lt and A_C for iteration k
-hipError_t launch_pack(const LaunchCtx& c, bool transpose, const float* w, double eps);
+hipError_t launch_pack(const LaunchCtx& c, bool transpose, const double* w, double eps);
 hipError_t launch_pack_rows_from_lah(const LaunchCtx& c, double eps);
 hipError_t launch_cert_reduce(const LaunchCtx& c);
 hipError_t launch_repair_pack(const LaunchCtx& c);
 hipError_t launch_repair_reduce(const LaunchCtx& c);
-hipError_t launch_scatter(const float* src, const int* perm, int count, float* dst, hipStream_t s);
-hipError_t launch_gather(const float* src, const int* perm, int np, float* dst, hipStream_t s);
+hipError_t launch_scatter(const double* src, const int* perm, int count, double* dst, hipStream_t s);
+hipError_t launch_gather(const double* src, const int* perm, int np, double* dst, hipStream_t s);
 
 int choose_splits(int np_out, int ntiles_in);
 

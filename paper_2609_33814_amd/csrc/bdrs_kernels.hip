@@ -10,18 +10,23 @@
 // b_q = Q_q - Qc, and with a = P_p - Qc the exponent expands exactly as
 //     w2_q - kappa2 |a - b_q|^2 = A_q + (2 kappa2 a) . b_q - kappa2 |a|^2,
 //     A_q = w2_q - kappa2 |b_q|^2   (written by the producing epilogue),
-// i.e. d FMAs and one add per entry, then one v_exp_f32 and one add.  All
-// magnitudes stay of the order of the tile radius for the entries that
-// dominate the sum, so the rounding matches that of the difference form.
+// i.e. d FMAs and one add per entry, then one v_exp_f32 and one add.
 //
-// Stability without a per-entry max: a per-(output, tile) upper bound
-//     UB = max_q A_q + sum_d |2 kappa2 a_d| rad_d - kappa2 |a|^2
-// is compared with the lane's running shift M.  Only when UB > M + 64 does the
-// lane take the exact maximum of the tile first (and rescale its sum); so every
-// summed term is at most 2^64 and M never exceeds the true maximum (no
-// underflow of the leading terms).  Lanes of a wave hold 64 consecutive
-// outputs in tile order, i.e. neighbouring points, so they agree on which
-// tiles need the exact maximum.
+// Precision split.  The weights w grow like g / eps as the temperature falls,
+// so float32 values of that size would carry absolute errors u |g| / eps.  The
+// inner loop therefore only sees small numbers: A_q is stored relative to its
+// tile maximum, A'_q = A_q - Amax_t (float32), and the large per-(output, tile)
+// part base = Amax_t - kappa2 |a|^2 and the lane's running shift M are kept in
+// float64.  The summand is 2^{cm + B . b_q + A'_q} with cm = base - M (float32,
+// small for the tiles that dominate the sum).
+//
+// Stability without a per-entry max: the per-(output, tile) upper bound
+//     UB = base + sum_d |2 kappa2 a_d| rad_d  >=  max_q exponent
+// is compared with M.  Only when UB > M + 64 does the lane take the exact
+// maximum of the tile first (and rescale its sum), so every summed term is at
+// most 2^64 and M never exceeds the true maximum (no underflow of the leading
+// terms).  Lanes of a wave hold 64 consecutive outputs in tile order, i.e.
+// neighbouring points, so they agree on which tiles need the exact maximum.
 //
 // Each (block of 256 outputs, split of the input tiles) writes a partial
 // (M, S[, N]); the finish kernels merge the splits in float64 and run the
@@ -35,7 +40,6 @@ namespace bdrs {
 
 namespace {
 
-constexpr float kLog2e = 1.4426950408889634f;
 constexpr double kLog2eD = 1.4426950408889634074;
 constexpr double kLn2D = 0.69314718055994530942;
 constexpr float kThresh = 64.0f;
@@ -47,9 +51,9 @@ __device__ __forceinline__ double eps_of(const Ctrl* c, double eps_arg, int kshi
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
-__device__ __forceinline__ float wave_max(float v) {
+__device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
 
@@ -66,27 +70,28 @@ template <int D, bool CERT>
 __global__ __launch_bounds__(kBlock) void k_sweep(
     const float* __restrict__ out_abs, int np_out,
     const float* __restrict__ in_off, const float* __restrict__ in_hdr,
-    const float* __restrict__ in_A, const float* __restrict__ in_Amax,
+    const float* __restrict__ in_A, const double* __restrict__ in_Amax,
     int ntiles_in, int tps,
-    float* __restrict__ pM, float* __restrict__ pS, float* __restrict__ pN,
+    double* __restrict__ pM, float* __restrict__ pS, float* __restrict__ pN,
     const Ctrl* __restrict__ ctrl, double eps_arg) {
   const int p = blockIdx.x * kBlock + threadIdx.x;
   const int split = blockIdx.y;
   const int t0 = split * tps;
   const int t1 = min(t0 + tps, ntiles_in);
   const double eps = eps_of(ctrl, eps_arg, 0);
-  const float kap2 = (float)(kLog2eD * ctrl->scale / eps);
-  const float kap2x2 = 2.0f * kap2;
+  const double kap2d = kLog2eD * ctrl->scale / eps;
+  const float kap2x2 = (float)(2.0 * kap2d);
 
   float P[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) P[d] = out_abs[(size_t)d * np_out + p];
 
-  float M = -INFINITY, S = 0.0f, N = 0.0f;
+  double M = -INFINITY;
+  float S = 0.0f, N = 0.0f;
 
   for (int t = t0; t < t1; ++t) {
     const float* __restrict__ hdr = in_hdr + (size_t)t * kHdr;
-    const float amax = in_Amax[t];
+    const double amax = in_Amax[t];
     if (amax == -INFINITY) continue;  // tile carries no mass (masked weights)
     float a[D], B[D], na = 0.0f;
 #pragma unroll
@@ -95,32 +100,33 @@ __global__ __launch_bounds__(kBlock) void k_sweep(
       na = fmaf(a[d], a[d], na);
       B[d] = kap2x2 * a[d];
     }
-    const float crow = -kap2 * na;
-    float ub = amax + crow;
+    const double base = amax - kap2d * (double)na;  // Amax_t - kappa2 |a|^2
+    float bnd = 0.0f;
 #pragma unroll
-    for (int d = 0; d < D; ++d) ub = fmaf(fabsf(B[d]), hdr[3 + d], ub);
+    for (int d = 0; d < D; ++d) bnd = fmaf(fabsf(B[d]), hdr[3 + d], bnd);
 
     const float* __restrict__ offs = in_off + (size_t)t * D * kTile;
     const float* __restrict__ Aq = in_A + (size_t)t * kTile;
 
-    if (ub > M + kThresh) {
+    if (base + (double)bnd > M + kThresh) {
       // exact maximum of this tile for the lanes whose bound exceeds the window
       float tm = -INFINITY;
 #pragma unroll 16
       for (int q = 0; q < kTile; ++q) {
-        float z = Aq[q] + crow;
+        float z = Aq[q];
 #pragma unroll
         for (int d = 0; d < D; ++d) z = fmaf(B[d], offs[d * kTile + q], z);
         tm = fmaxf(tm, z);
       }
-      if (tm > M) {
-        const float sc = fast_exp2(M - tm);
+      const double tmd = base + (double)tm;
+      if (tmd > M) {
+        const float sc = fast_exp2((float)(M - tmd));
         S *= sc;
         if (CERT) N *= sc;
-        M = tm;
+        M = tmd;
       }
     }
-    const float cm = crow - M;
+    const float cm = (float)(base - M);
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
     float n0 = 0.f, n1 = 0.f;
 #pragma unroll 16
@@ -166,25 +172,25 @@ struct Merged {
   double N;     // merged shifted cost sum
 };
 
-__device__ __forceinline__ Merged merge_splits(const float* __restrict__ pM, const float* __restrict__ pS,
+__device__ __forceinline__ Merged merge_splits(const double* __restrict__ pM, const float* __restrict__ pS,
                                                const float* __restrict__ pN, int splits, int np, int p,
                                                bool cert) {
-  float mx = -INFINITY;
-  for (int s = 0; s < splits; ++s) mx = fmaxf(mx, pM[(size_t)s * np + p]);
+  double mx = -INFINITY;
+  for (int s = 0; s < splits; ++s) mx = fmax(mx, pM[(size_t)s * np + p]);
   Merged r{-INFINITY, 0.0, 0.0};
   if (mx == -INFINITY) return r;  // empty sum
   double S = 0.0, N = 0.0;
   for (int s = 0; s < splits; ++s) {
     const size_t o = (size_t)s * np + p;
-    const float ms = pM[o];
+    const double ms = pM[o];
     if (ms == -INFINITY) continue;
-    const double w = exp2((double)ms - (double)mx);
+    const double w = exp2(ms - mx);
     S += w * (double)pS[o];
     if (cert) N += w * (double)pN[o];
   }
   r.S = S;
   r.N = N;
-  r.lse = kLn2D * ((double)mx + log2(S));
+  r.lse = kLn2D * (mx + log2(S));
   return r;
 }
 
@@ -198,19 +204,21 @@ __device__ __forceinline__ float norm2_off(const float* __restrict__ off, int di
   return s;
 }
 
-// Writes A_p = log2(e) w - kappa2 |b_p|^2 (or -inf on padding) and the tile max.
+// A_p = log2(e) w - kappa2 |b_p|^2 in float64 (-inf on padding or for w = -inf);
+// stores the tile maximum (float64) and A_p minus that maximum (float32).
+// Called by whole wavefronts (one tile per wavefront).
 __device__ __forceinline__ void pack_weight(const SideDev& sd, int dim, int p, double w, double kap2) {
-  float A = -INFINITY;
-  if (p < sd.count) A = (float)(kLog2eD * w - kap2 * (double)norm2_off(sd.off, dim, p));
+  double A = -INFINITY;
+  if (p < sd.count && w > -INFINITY) A = kLog2eD * w - kap2 * (double)norm2_off(sd.off, dim, p);
   if (p < sd.ntiles * kTile) {
-    sd.A[p] = A;
-    const float m = wave_max(A);
+    const double m = wave_max(A);
+    sd.A[p] = (A == -INFINITY) ? -INFINITY : (float)(A - m);
     if ((threadIdx.x & (kTile - 1)) == 0) sd.Amax[p / kTile] = m;
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_finish(LaunchCtx c, int transpose, int kind, int splits,
-                                                   double eps_arg, float* __restrict__ lse_out) {
+                                                   double eps_arg, double* __restrict__ lse_out) {
   const SideDev& out = transpose ? c.cols : c.rows;
   const int p = blockIdx.x * kBlock + threadIdx.x;
   const int np = out.np;
@@ -223,20 +231,20 @@ __global__ __launch_bounds__(kBlock) void k_finish(LaunchCtx c, int transpose, i
   const double lam = ctrl->lam;
 
   if (kind == kFinishLse) {
-    if (real) lse_out[out.perm[p]] = (float)mg.lse;
+    if (real) lse_out[out.perm[p]] = mg.lse;
     return;
   }
   if (kind == kFinishCertOnly) {
     // Algorithm 2 for the last finished iteration k-1 (k has been advanced)
     if (real) {
       c.st.mu[p] = ctrl->scale * mg.N / mg.S;
-      c.st.logs[p] = (double)c.st.lt[(k - 1) & 1][p] + mg.lse;
+      c.st.logs[p] = c.st.lt[(k - 1) & 1][p] + mg.lse;
     }
     return;
   }
   if (kind == kFinishRepair) {
     // p_i = A_i sum_j K_ij t_j (1 - e_j) = exp(log alpha-hat_i + LSE_i)
-    c.st.pvec[p] = real ? exp((double)c.st.lah[p] + mg.lse) : 0.0;
+    c.st.pvec[p] = real ? exp(c.st.lah[p] + mg.lse) : 0.0;
     return;
   }
   if (kind == kFinishRow) {
@@ -246,11 +254,11 @@ __global__ __launch_bounds__(kBlock) void k_finish(LaunchCtx c, int transpose, i
     double lah = 0.0;
     if (real) {
       lah = out.logmarg[p] - mg.lse;
-      c.st.lah[p] = (float)lah;
-      c.st.la[p] = (float)((1.0 - lam) * (double)c.st.la[p] + lam * lah);
+      c.st.lah[p] = lah;
+      c.st.la[p] = (1.0 - lam) * c.st.la[p] + lam * lah;
     }
     // weights of the column sweep of the same iteration: w = log alpha-hat
-    pack_weight(c.rows, c.dim, p, (double)(float)lah, kap2);
+    pack_weight(c.rows, c.dim, p, lah, kap2);
     return;
   }
   // column epilogue (plain or certificate)
@@ -262,19 +270,17 @@ __global__ __launch_bounds__(kBlock) void k_finish(LaunchCtx c, int transpose, i
     if (cert) {
       // Algorithm 2: mu_j = N_j / D_j, d_j = M_j + log D_j, log s_j = log t_j + d_j
       c.st.mu[p] = ctrl->scale * mg.N / mg.S;
-      c.st.logs[p] = (double)c.st.lt[cur][p] + mg.lse;
+      c.st.logs[p] = c.st.lt[cur][p] + mg.lse;
     }
-    c.st.lbh[p] = (float)lbh;
-    const float lbf = (float)lb;
-    c.st.lb2[p] = (float)lb1;
-    c.st.lb1[p] = lbf;
+    c.st.lbh[p] = lbh;
+    c.st.lb2[p] = lb1;
+    c.st.lb1[p] = lb;
     // momentum for iteration k+1: log beta-tilde^k = log beta^k + (log beta^k - log beta^{k-1}) / lambda
-    const double lt = (double)lbf + ((double)lbf - lb1) / lam;
-    c.st.lt[nxt][p] = (float)lt;
+    c.st.lt[nxt][p] = lb + (lb - lb1) / lam;
   }
   const double eps1 = eps_of(ctrl, -1.0, 1);
   const double kap2n = kLog2eD * ctrl->scale / eps1;
-  pack_weight(c.cols, c.dim, p, real ? (double)c.st.lt[nxt][p] : 0.0, kap2n);
+  pack_weight(c.cols, c.dim, p, real ? c.st.lt[nxt][p] : 0.0, kap2n);
 
   // the last block to finish advances k (all blocks have read it by then)
   __syncthreads();
@@ -300,20 +306,20 @@ __global__ __launch_bounds__(kBlock) void k_prologue(LaunchCtx c) {
   if (real) {
     const double lb1 = c.st.lb1[p], lb2 = c.st.lb2[p];
     lt = lb1 + (lb1 - lb2) / lam;
-    c.st.lt[k & 1][p] = (float)lt;
+    c.st.lt[k & 1][p] = lt;
   }
   const double kap2 = kLog2eD * c.ctrl->scale / eps_of(c.ctrl, -1.0, 0);
-  pack_weight(c.cols, c.dim, p, (double)(float)lt, kap2);
+  pack_weight(c.cols, c.dim, p, lt, kap2);
 }
 
 // A of the input side from caller weights w (original order), for bdrs_lse.
-__global__ __launch_bounds__(kBlock) void k_pack(LaunchCtx c, int transpose, const float* __restrict__ w,
+__global__ __launch_bounds__(kBlock) void k_pack(LaunchCtx c, int transpose, const double* __restrict__ w,
                                                  double eps) {
   const SideDev& in = transpose ? c.rows : c.cols;
   const int p = blockIdx.x * kBlock + threadIdx.x;
   if (p >= in.np) return;
   const double kap2 = kLog2eD * c.ctrl->scale / eps;
-  const double wv = p < in.count ? (double)w[in.perm[p]] : 0.0;
+  const double wv = p < in.count ? w[in.perm[p]] : 0.0;
   pack_weight(in, c.dim, p, wv, kap2);
 }
 
@@ -322,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_rows(LaunchCtx c, double eps) {
   const int p = blockIdx.x * kBlock + threadIdx.x;
   if (p >= c.rows.np) return;
   const double kap2 = kLog2eD * c.ctrl->scale / eps;
-  pack_weight(c.rows, c.dim, p, p < c.rows.count ? (double)c.st.lah[p] : 0.0, kap2);
+  pack_weight(c.rows, c.dim, p, p < c.rows.count ? c.st.lah[p] : 0.0, kap2);
 }
 
 // Repair weights: log t_j + log(1 - e_j), e_j = min(1, c_j / s_j) (-inf where e_j = 1).
@@ -334,17 +340,10 @@ __global__ __launch_bounds__(kBlock) void k_repair_pack(LaunchCtx c) {
   if (p < c.cols.count) {
     const double s = exp(c.st.logs[p]);
     const double cj = c.cols.marg[p];
-    if (s > cj) w = (double)c.st.lt[k & 1][p] + log1p(-cj / s);
+    if (s > cj) w = c.st.lt[k & 1][p] + log1p(-cj / s);
   }
   const double kap2 = kLog2eD * c.ctrl->scale / eps_of(c.ctrl, -1.0, -1);
-  const SideDev& in = c.cols;
-  float A = -INFINITY;
-  if (p < in.count && w > -INFINITY) A = (float)(kLog2eD * w - kap2 * (double)norm2_off(in.off, c.dim, p));
-  if (p < in.ntiles * kTile) {
-    in.A[p] = A;
-    const float m = wave_max(A);
-    if ((threadIdx.x & (kTile - 1)) == 0) in.Amax[p / kTile] = m;
-  }
+  pack_weight(c.cols, c.dim, p, w, kap2);
 }
 
 // ---------------------------------------------------------------------------
@@ -482,14 +481,14 @@ __global__ __launch_bounds__(kBlock) void k_repair_final(LaunchCtx c) {
   }
 }
 
-__global__ void k_scatter(const float* __restrict__ src, const int* __restrict__ perm, int count,
-                          float* __restrict__ dst) {
+__global__ void k_scatter(const double* __restrict__ src, const int* __restrict__ perm, int count,
+                          double* __restrict__ dst) {
   const int p = blockIdx.x * kBlock + threadIdx.x;
   if (p < count) dst[perm[p]] = src[p];
 }
 
-__global__ void k_gather(const float* __restrict__ src, const int* __restrict__ perm, int np,
-                         float* __restrict__ dst) {
+__global__ void k_gather(const double* __restrict__ src, const int* __restrict__ perm, int np,
+                         double* __restrict__ dst) {
   const int p = blockIdx.x * kBlock + threadIdx.x;
   if (p < np) dst[p] = src[perm[p]];
 }
@@ -530,7 +529,7 @@ hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int split
 }
 
 hipError_t launch_finish(const LaunchCtx& c, bool transpose, FinishKind kind, int splits, double eps_arg,
-                         float* lse_out) {
+                         double* lse_out) {
   const SideDev& out = transpose ? c.cols : c.rows;
   hipLaunchKernelGGL(k_finish, dim3(out.np / kBlock), dim3(kBlock), 0, c.stream, c, transpose ? 1 : 0,
                      (int)kind, splits, eps_arg, lse_out);
@@ -542,7 +541,7 @@ hipError_t launch_prologue(const LaunchCtx& c) {
   return hipGetLastError();
 }
 
-hipError_t launch_pack(const LaunchCtx& c, bool transpose, const float* w, double eps) {
+hipError_t launch_pack(const LaunchCtx& c, bool transpose, const double* w, double eps) {
   const SideDev& in = transpose ? c.rows : c.cols;
   hipLaunchKernelGGL(k_pack, dim3(in.np / kBlock), dim3(kBlock), 0, c.stream, c, transpose ? 1 : 0, w, eps);
   return hipGetLastError();
@@ -570,13 +569,13 @@ hipError_t launch_repair_reduce(const LaunchCtx& c) {
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(const float* src, const int* perm, int count, float* dst, hipStream_t s) {
+hipError_t launch_scatter(const double* src, const int* perm, int count, double* dst, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, s, src, perm, count, dst);
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const float* src, const int* perm, int np, float* dst, hipStream_t s) {
+hipError_t launch_gather(const double* src, const int* perm, int np, double* dst, hipStream_t s) {
   if (np <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather, dim3((np + kBlock - 1) / kBlock), dim3(kBlock), 0, s, src, perm, np, dst);
   return hipGetLastError();

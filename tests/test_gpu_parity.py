@@ -2,11 +2,13 @@
 
 Tolerances (written here, derived in the design notes):
 * one LSE sweep: ||y_gpu - y_ref||_inf / max(1, ||y_ref||_inf) <= 1e-5, both
-  sides fed the same float32 inputs, y_ref in float64;
+  sides fed the same float64 weights (the kernel rounds them, relative to
+  their tile maximum, to float32), y_ref in float64;
 * the 500-iteration 32x32 trajectory: relative gap at the last certificate
   within 1e-3 relative of the oracle's own trajectory;
-* a certificate evaluated from an identical state: L and U within 1e-6
-  relative (float32 sweep, float64 sums).
+* a certificate evaluated from an identical (float64) state: L within 1e-9
+  relative (no sweep involved), U within 1e-5 relative (one float32 sweep,
+  float64 sums).
 """
 import numpy as np
 import pytest
@@ -42,13 +44,14 @@ def rel_err(got, ref):
     return float(np.max(np.abs(got - ref)) / max(1.0, float(np.max(np.abs(ref)))))
 
 
-def sweep_both(sv, prob, w32, eps, transpose):
-    """GPU sweep and the oracle's on identical float32 inputs."""
-    got = sv.lse(torch.as_tensor(w32, device=dev()), eps, transpose=transpose).cpu().numpy()
+def sweep_both(sv, prob, w, eps, transpose):
+    """GPU sweep and the oracle's on identical float64 weights."""
+    w = np.asarray(w, dtype=np.float64)
+    got = sv.lse(torch.as_tensor(w, device=dev()), eps, transpose=transpose).cpu().numpy()
     if transpose:
-        ref = lse.implicit_lse(prob.y, prob.x, prob.cost_scale, eps, w32.astype(np.float64))
+        ref = lse.implicit_lse(prob.y, prob.x, prob.cost_scale, eps, w)
     else:
-        ref = lse.implicit_lse(prob.x, prob.y, prob.cost_scale, eps, w32.astype(np.float64))
+        ref = lse.implicit_lse(prob.x, prob.y, prob.cost_scale, eps, w)
     return got, ref
 
 
@@ -75,7 +78,7 @@ def test_sweep_parity_random_weights(name, make, eps):
     rng = np.random.default_rng(17)
     for transpose in (False, True):
         n_in = prob.m if transpose else prob.n
-        w = rng.normal(0.0, 20.0, n_in).astype(np.float32)
+        w = rng.normal(0.0, 20.0, n_in)
         got, ref = sweep_both(sv, prob, w, eps, transpose)
         assert rel_err(got, ref) <= SWEEP_TOL, (name, eps, transpose, rel_err(got, ref))
 
@@ -88,11 +91,11 @@ def test_sweep_duplicate_points_and_masked_weights():
     c = np.full(200, 1 / 200)
     prob = inputs.Problem(x=x, y=y, r=r, c=c, cost_scale=1.0)
     sv = solver_for(prob)
-    w = rng.normal(0, 5, 200).astype(np.float32)
+    w = rng.normal(0, 5, 200)
     w[::3] = -np.inf                                                    # masked columns
     got, ref = sweep_both(sv, prob, w, 0.01, False)
     assert rel_err(got, ref) <= SWEEP_TOL
-    w_all = np.full(200, -np.inf, dtype=np.float32)                     # empty sum -> -inf
+    w_all = np.full(200, -np.inf)                                       # empty sum -> -inf
     got = sv.lse(torch.as_tensor(w_all, device=dev()), 0.01).cpu().numpy()
     assert np.all(got == -np.inf)
 
@@ -114,9 +117,9 @@ def test_c1_sweep_parity_on_trajectory_states(c1_oracle, k):
     st = states[k]
     eps = alg1.schedule(1.0, 1.0, k)
     sv = solver_for(prob)
-    got, ref = sweep_both(sv, prob, st.lt.astype(np.float32), eps, False)
+    got, ref = sweep_both(sv, prob, st.lt, eps, False)
     assert rel_err(got, ref) <= SWEEP_TOL, rel_err(got, ref)
-    got, ref = sweep_both(sv, prob, st.lah.astype(np.float32), eps, True)
+    got, ref = sweep_both(sv, prob, st.lah, eps, True)
     assert rel_err(got, ref) <= SWEEP_TOL, rel_err(got, ref)
 
 
@@ -128,14 +131,15 @@ def test_c1_trajectory_parity(c1_oracle):
     ref = certs_ref[-1]
     assert ref["k"] == 499
     rel_ref = ref["rel"]
+    print("c1 final gap rel err", abs(ce["rel_gap"] - rel_ref) / rel_ref)
     assert abs(ce["rel_gap"] - rel_ref) / rel_ref <= 1e-3, (ce["rel_gap"], rel_ref)
     assert abs(ce["U"] - ref["U"]) / ref["U"] <= 1e-4
     assert abs(ce["L"] - ref["L"]) / abs(ref["L"]) <= 1e-4
     # potentials f = eps log A, g = eps log(B / c)
     gs = sv.get_state()
     eps = ref["eps"]
-    f_gpu = eps * gs["lah"].cpu().numpy().astype(np.float64)
-    g_gpu = eps * (gs["lbh"].cpu().numpy().astype(np.float64) - np.log(prob.c))
+    f_gpu = eps * gs["lah"].cpu().numpy()
+    g_gpu = eps * (gs["lbh"].cpu().numpy() - np.log(prob.c))
     assert rel_err(f_gpu, ref["f"]) <= 1e-4
     assert rel_err(g_gpu, ref["g"]) <= 1e-4
     assert gs["k"] == 500
@@ -145,21 +149,19 @@ def test_certificate_from_identical_state(c1_oracle):
     prob, _, _, states = c1_oracle
     k = 199
     st = states[k]
-    r32 = lambda a: a.astype(np.float32)
     d = dev()
+    T = lambda a: torch.as_tensor(a, device=d)
     sv = solver_for(prob)
-    sv.set_state(dict(la=torch.as_tensor(r32(st.la), device=d), lb=torch.as_tensor(r32(st.lb1), device=d),
-                      lb_prev=torch.as_tensor(r32(st.lb2), device=d), lah=torch.as_tensor(r32(st.lah), device=d),
-                      lbh=torch.as_tensor(r32(st.lbh), device=d), lt=torch.as_tensor(r32(st.lt), device=d),
-                      k=k + 1))
+    sv.set_state(dict(la=T(st.la), lb=T(st.lb1), lb_prev=T(st.lb2), lah=T(st.lah), lbh=T(st.lbh),
+                      lt=T(st.lt), k=k + 1))
     ce = sv.certificate()
     eps = alg1.schedule(1.0, 1.0, k)
-    ref = certificate.certificate(prob.x, prob.y, prob.cost_scale, prob.r, prob.c,
-                                  r32(st.lah).astype(np.float64), r32(st.lbh).astype(np.float64),
-                                  r32(st.lt).astype(np.float64), eps)
+    ref = certificate.certificate(prob.x, prob.y, prob.cost_scale, prob.r, prob.c, st.lah, st.lbh, st.lt, eps)
+    print("cert identical state: dL", abs(ce["L"] - ref["L"]) / abs(ref["L"]),
+          "dU", abs(ce["U"] - ref["U"]) / ref["U"], "ddelta", abs(ce["delta"] - ref["delta"]) / ref["delta"])
     assert ce["k"] == k
-    assert abs(ce["L"] - ref["L"]) <= 1e-6 * abs(ref["L"])
-    assert abs(ce["U"] - ref["U"]) <= 1e-6 * abs(ref["U"])
+    assert abs(ce["L"] - ref["L"]) <= 1e-9 * abs(ref["L"])
+    assert abs(ce["U"] - ref["U"]) <= 1e-5 * abs(ref["U"])
     assert abs(ce["delta"] - ref["delta"]) <= 1e-4 * ref["delta"] + 1e-9
     assert ce["n_nonfinite"] == 0
 
@@ -175,6 +177,7 @@ def test_obdrs_trajectory_parity(lam):
     ok, ce = sv.solve(0.0, 200, 50)
     ref = certs[-1]
     assert ce["k"] == ref["k"] == 199
+    print("obdrs", lam, "gap rel err", abs(ce["rel_gap"] - ref["rel"]) / ref["rel"])
     assert abs(ce["rel_gap"] - ref["rel"]) / ref["rel"] <= 1e-3
     assert abs(ce["U"] - ref["U"]) / ref["U"] <= 1e-4
 
@@ -217,15 +220,16 @@ def test_repaired_cost_parity_and_bracket(lam):
     ce = sv.certificate()
     gs = sv.get_state()
     eps = alg1.schedule(0.5, lam, 59)
-    lah = gs["lah"].cpu().numpy().astype(np.float64)
-    lt = gs["lt"].cpu().numpy().astype(np.float64)
-    lbh = gs["lbh"].cpu().numpy().astype(np.float64)
+    lah = gs["lah"].cpu().numpy()
+    lt = gs["lt"].cpu().numpy()
+    lbh = gs["lbh"].cpu().numpy()
     ref = certificate.certificate(prob.x, prob.y, prob.cost_scale, prob.r, prob.c, lah, lbh, lt, eps)
     rp = repair.dense_repair(prob.x, prob.y, prob.cost_scale, prob.r, prob.c, lah, lt, eps)
-    assert abs(ce["repaired_cost"] - rp["cost_Zhat"]) <= 1e-6 * rp["cost_Zhat"]
+    print("repaired cost rel err", abs(ce["repaired_cost"] - rp["cost_Zhat"]) / rp["cost_Zhat"])
+    assert abs(ce["repaired_cost"] - rp["cost_Zhat"]) <= 1e-5 * rp["cost_Zhat"]
     assert ce["L"] <= pstar + 1e-7 and pstar <= ce["repaired_cost"] + 1e-7
     assert ce["repaired_cost"] <= ce["U"] + 1e-7
-    assert abs(ce["U"] - ref["U"]) <= 1e-6 * ref["U"]
+    assert abs(ce["U"] - ref["U"]) <= 1e-5 * ref["U"]
 
 
 def test_bracket_exact_1d_optimum_large():
@@ -252,7 +256,7 @@ def test_full_size_grid_sampled_rows():
     rng = np.random.default_rng(23)
     rows = rng.choice(prob.m, 256, replace=False)
     for eps in (1.0, 2e-3):
-        w = rng.normal(0, 30, prob.n).astype(np.float32)
+        w = rng.normal(0, 30, prob.n)
         got = sv.lse(torch.as_tensor(w, device=dev()), eps).cpu().numpy()[rows]
-        ref = lse.implicit_lse(prob.x, prob.y, prob.cost_scale, eps, w.astype(np.float64), rows=rows)
+        ref = lse.implicit_lse(prob.x, prob.y, prob.cost_scale, eps, w, rows=rows)
         assert rel_err(got, ref) <= SWEEP_TOL
