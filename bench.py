@@ -67,6 +67,9 @@ def main() -> int:
     ap.add_argument("--no-ttg", action="store_true", help="skip the time-to-1%% runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--ttg-cap", type=int, default=20000)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (known bytes) so that "
+                         "HBM traffic counters can be scaled")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver is "
@@ -122,6 +125,15 @@ def main() -> int:
                                     "U_best": ce["U_best"], "L_best": ce["L_best"]}
             print(f"[bench] time-to-1% lambda={lam}: {ttg[f'lambda={lam}']}", flush=True)
             s2.close()
+
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)   # 256 MiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: 268435456 bytes read, 268435456 bytes written", flush=True)
+        del src, dst
 
     cpu = None if args.no_cpu else cpu_baseline(prob)
     line = {

@@ -126,7 +126,9 @@ BDRS_API bdrs_status bdrs_create(const bdrs_params *p, bdrs_solver *out);
 
 /* Runs `iters` >= 0 iterations of Algorithm 1 (schedule, momentum, row
  * sweep, overrelaxation, column sweep, overrelaxation) without a
- * certificate.  Asynchronous on the solver's stream. */
+ * certificate.  Asynchronous on the solver's stream; enqueues kernels only
+ * and keeps the iteration counter in device memory, so a stream capture of
+ * bdrs_step can be replayed as a block of iterations. */
 BDRS_API bdrs_status bdrs_step(bdrs_solver s, int32_t iters);
 
 /* Certificate of the last finished iteration (Prop. 3 / Algorithm 2): one
@@ -173,7 +175,7 @@ BDRS_API bdrs_status bdrs_set_state(bdrs_solver s, const double *log_alpha,
  * w and out are device float64 in original point order (length n / m resp.
  * m / n); the sweep itself runs in float32 on weights taken relative to
  * their tile maximum.  Uses the solver's workspace (clobbers its sweep buffers but not
- * the dual state).  Asynchronous. */
+ * the dual state).  Synchronises the stream. */
 BDRS_API bdrs_status bdrs_lse(bdrs_solver s, int32_t transpose, double eps,
                      const double *w, double *out);
 

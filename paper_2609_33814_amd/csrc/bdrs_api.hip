@@ -66,7 +66,7 @@ struct Layout {
   size_t r_abs, r_off, r_hdr, r_A, r_Amax, r_perm, r_marg, r_logm;
   size_t c_abs, c_off, c_hdr, c_A, c_Amax, c_perm, c_marg, c_logm;
   size_t la, lah, lb1, lb2, lbh, lt0, lt1, mu, logs, pvec;
-  size_t pM, pS, pN, cert_part, cert_out;
+  size_t part, cert_part, cert_out;
 };
 
 Layout make_layout(int m, int n, int dim) {
@@ -109,9 +109,7 @@ Layout make_layout(int m, int n, int dim) {
   L.logs = take(sizeof(double) * L.C.np);
   L.pvec = take(sizeof(double) * L.R.np);
   const size_t pelems = (size_t)std::max((size_t)L.splits_row * L.R.np, (size_t)L.splits_col * L.C.np);
-  L.pM = take(sizeof(double) * pelems);
-  L.pS = take(sizeof(float) * pelems);
-  L.pN = take(sizeof(float) * pelems);
+  L.part = take(sizeof(PartialRec) * pelems);
   L.cert_part = take(sizeof(double) * 2 * (size_t)L.cert_blocks * 8);
   L.cert_out = take(sizeof(double) * kCertSlots);
   L.total = o;
@@ -255,7 +253,8 @@ struct bdrs_solver_ {
   bdrs_params prm;
   Layout L;
   LaunchCtx ctx;
-  long long k = 0;          // finished iterations (mirrors Ctrl::k)
+  long long k = 0;          // finished iterations, refreshed from Ctrl::k by sync_k (the
+                            // device counter is the truth: captured graphs advance it)
   double U_best = INFINITY, L_best = -INFINITY;
   long long kU = -1, kL = -1;
   bool packed_rows = false; // rows.A holds log alpha-hat of iteration k-1
@@ -303,13 +302,20 @@ void fill_ctx(bdrs_solver s) {
   c.st.mu = (double*)(base + L.mu);
   c.st.logs = (double*)(base + L.logs);
   c.st.pvec = (double*)(base + L.pvec);
-  c.part.M = (double*)(base + L.pM);
-  c.part.S = (float*)(base + L.pS);
-  c.part.N = (float*)(base + L.pN);
+  c.part.rec = (PartialRec*)(base + L.part);
   c.part.splits = L.splits_max;
   c.cert_part = (double*)(base + L.cert_part);
   c.cert_out = (double*)(base + L.cert_out);
   c.cert_blocks = L.cert_blocks;
+}
+
+// reads the device iteration counter (synchronises the stream)
+bdrs_status sync_k(bdrs_solver s) {
+  long long k = 0;
+  HIPCHK(hipMemcpyAsync(&k, &s->ctx.ctrl->k, sizeof k, hipMemcpyDeviceToHost, s->ctx.stream));
+  HIPCHK(hipStreamSynchronize(s->ctx.stream));
+  s->k = k;
+  return BDRS_OK;
 }
 
 double eps_at(const bdrs_solver s, long long k) { return s->prm.eta / (s->prm.lambda * (double)k + 1.0); }
@@ -543,8 +549,9 @@ bdrs_status bdrs_step(bdrs_solver s, int32_t iters) {
 bdrs_status bdrs_certificate(bdrs_solver s, bdrs_cert* out) {
   if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
   if (!out) return fail(BDRS_E_INVALID, "out is NULL");
+  bdrs_status st = sync_k(s);
+  if (st != BDRS_OK) return st;
   if (s->k < 1) return fail(BDRS_E_STATE, "no iteration has run yet");
-  bdrs_status st;
   if (!s->packed_rows && (st = repack(s)) != BDRS_OK) return st;
   const LaunchCtx& c = s->ctx;
   const double eps = eps_at(s, s->k - 1);
@@ -567,6 +574,8 @@ bdrs_status bdrs_solve(bdrs_solver s, double tau, int32_t tau_relative, int32_t 
   const bool repair = (s->prm.flags & BDRS_F_REPAIR) != 0;
   bdrs_cert ce{};
   bool have = false;
+  bdrs_status st0 = sync_k(s);
+  if (st0 != BDRS_OK) return st0;
   for (int32_t i = 0; i < max_iters; ++i) {
     const long long k = s->k;
     const bool due = ((k + 1) % cert_every == 0) || (i == max_iters - 1);
@@ -595,6 +604,8 @@ bdrs_status bdrs_solve(bdrs_solver s, double tau, int32_t tau_relative, int32_t 
 bdrs_status bdrs_get_state(bdrs_solver s, double* log_alpha, double* log_beta, double* log_beta_prev,
                            double* log_alpha_hat, double* log_beta_hat, double* log_beta_tilde, int64_t* iters_done) {
   if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  bdrs_status st = sync_k(s);
+  if (st != BDRS_OK) return st;
   const LaunchCtx& c = s->ctx;
   hipError_t e = hipSuccess;
   auto sc = [&](const double* src, const SideDev& sd, double* dst) {
@@ -659,6 +670,8 @@ bdrs_status bdrs_lse(bdrs_solver s, int32_t transpose, double eps, const double*
   const int splits = tr ? s->L.splits_col : s->L.splits_row;
   hipError_t e;
   if ((e = launch_pack(c, tr, w, eps)) != hipSuccess) return hip_status(e, "pack");
+  bdrs_status st = sync_k(s);
+  if (st != BDRS_OK) return st;
   if ((e = sweep(s, tr, false, splits, eps)) != hipSuccess) return hip_status(e, "sweep");
   if ((e = launch_finish(c, tr, kFinishLse, splits, eps, out)) != hipSuccess) return hip_status(e, "finish");
   s->packed_rows = false;

@@ -10,6 +10,11 @@ constexpr int kBlock = 256;       // threads per block in every kernel
 constexpr int kHdr = 8;           // floats per tile header: center[3], radius[3], pad[2]
 constexpr int kCertSlots = 16;    // doubles in a certificate record
 
+// (output wavefront, split) pairs a sweep aims for: 4 per SIMD on 256 CUs
+#ifndef BDRS_TARGET_WAVES
+#define BDRS_TARGET_WAVES 4096
+#endif
+
 // Device-resident control block of one solver: the iteration counter lives
 // here so that a captured block of iterations can be replayed at any k.
 struct Ctrl {
@@ -51,11 +56,16 @@ struct StateDev {
   double* pvec;     // repair: row deficits p_i
 };
 
+// Partial reduction of one (split, output): shift M (log2, float64), shifted
+// sum S and shifted cost-weighted sum N (certificate sweeps).  16 bytes.
+struct PartialRec {
+  double M;
+  float S, N;
+};
+
 struct Partials {
-  double* M;  // [S][np] running shift (log2, float64)
-  float* S;   // [S][np] shifted sum
-  float* N;   // [S][np] shifted cost-weighted sum (certificate sweeps)
-  int splits; // allocated splits
+  PartialRec* rec;  // [S][np]
+  int splits;       // allocated splits
 };
 
 enum FinishKind {

@@ -72,8 +72,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(
     const float* __restrict__ in_off, const float* __restrict__ in_hdr,
     const float* __restrict__ in_A, const double* __restrict__ in_Amax,
     int ntiles_in, int tps,
-    double* __restrict__ pM, float* __restrict__ pS, float* __restrict__ pN,
-    const Ctrl* __restrict__ ctrl, double eps_arg) {
+    PartialRec* __restrict__ part, const Ctrl* __restrict__ ctrl, double eps_arg) {
   const int p = blockIdx.x * kBlock + threadIdx.x;
   const int split = blockIdx.y;
   const int t0 = split * tps;
@@ -157,10 +156,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep(
     S += (s0 + s1) + (s2 + s3);
     if (CERT) N += n0 + n1;
   }
-  const size_t o = (size_t)split * np_out + p;
-  pM[o] = M;
-  pS[o] = S;
-  if (CERT) pN[o] = N;
+  PartialRec rec;
+  rec.M = M;
+  rec.S = S;
+  rec.N = CERT ? N : 0.0f;
+  part[(size_t)split * np_out + p] = rec;
 }
 
 // ---------------------------------------------------------------------------
@@ -172,21 +172,35 @@ struct Merged {
   double N;     // merged shifted cost sum
 };
 
-__device__ __forceinline__ Merged merge_splits(const double* __restrict__ pM, const float* __restrict__ pS,
-                                               const float* __restrict__ pN, int splits, int np, int p,
-                                               bool cert) {
+__device__ __forceinline__ Merged merge_splits(const PartialRec* __restrict__ part, int splits, int np,
+                                               int p) {
+  // all loads of a group of 8 splits are issued before they are used
+  constexpr int G = 8;
   double mx = -INFINITY;
-  for (int s = 0; s < splits; ++s) mx = fmax(mx, pM[(size_t)s * np + p]);
+  for (int s0 = 0; s0 < splits; s0 += G) {
+    double m[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) m[g] = (s0 + g < splits) ? part[(size_t)(s0 + g) * np + p].M : -INFINITY;
+#pragma unroll
+    for (int g = 0; g < G; ++g) mx = fmax(mx, m[g]);
+  }
   Merged r{-INFINITY, 0.0, 0.0};
   if (mx == -INFINITY) return r;  // empty sum
   double S = 0.0, N = 0.0;
-  for (int s = 0; s < splits; ++s) {
-    const size_t o = (size_t)s * np + p;
-    const double ms = pM[o];
-    if (ms == -INFINITY) continue;
-    const double w = exp2(ms - mx);
-    S += w * (double)pS[o];
-    if (cert) N += w * (double)pN[o];
+  for (int s0 = 0; s0 < splits; s0 += G) {
+    PartialRec q[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (s0 + g < splits) q[g] = part[(size_t)(s0 + g) * np + p];
+      else q[g] = PartialRec{-INFINITY, 0.0f, 0.0f};
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      // shifts of one output differ by little: the weight is a hardware float32 exp2
+      const double w = (double)fast_exp2((float)(q[g].M - mx));  // 0 for an empty split
+      S += w * (double)q[g].S;
+      N += w * (double)q[g].N;
+    }
   }
   r.S = S;
   r.N = N;
@@ -217,14 +231,14 @@ __device__ __forceinline__ void pack_weight(const SideDev& sd, int dim, int p, d
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_finish(LaunchCtx c, int transpose, int kind, int splits,
-                                                   double eps_arg, double* __restrict__ lse_out) {
+__global__ __launch_bounds__(kTile) void k_finish(LaunchCtx c, int transpose, int kind, int splits,
+                                                  double eps_arg, double* __restrict__ lse_out) {
   const SideDev& out = transpose ? c.cols : c.rows;
-  const int p = blockIdx.x * kBlock + threadIdx.x;
+  const int p = blockIdx.x * kTile + threadIdx.x;
   const int np = out.np;
   if (p >= np) return;
   const bool cert = (kind == kFinishColCert || kind == kFinishCertOnly);
-  const Merged mg = merge_splits(c.part.M, c.part.S, c.part.N, splits, np, p, cert);
+  const Merged mg = merge_splits(c.part.rec, splits, np, p);
   const bool real = p < out.count;
   const Ctrl* ctrl = c.ctrl;
   const long long k = ctrl->k;
@@ -282,15 +296,13 @@ __global__ __launch_bounds__(kBlock) void k_finish(LaunchCtx c, int transpose, i
   const double kap2n = kLog2eD * ctrl->scale / eps1;
   pack_weight(c.cols, c.dim, p, real ? c.st.lt[nxt][p] : 0.0, kap2n);
 
-  // the last block to finish advances k (all blocks have read it by then)
-  __syncthreads();
+  // the last block to finish advances k: every block read k at its start and
+  // used it before counting itself here, and the next kernel sees the store
   if (threadIdx.x == 0) {
-    __threadfence();
     const unsigned int done = atomicAdd(&c.ctrl->arrive, 1u);
     if (done == gridDim.x - 1) {
       c.ctrl->arrive = 0u;
       c.ctrl->k = k + 1;
-      __threadfence();
     }
   }
 }
@@ -499,11 +511,12 @@ int choose_splits(int np_out, int ntiles_in) {
   // enough (output wave, split) pairs to give every SIMD of the 256 CUs a few
   // waves, but at least 4 tiles per split so the per-split set-up stays small
   const int out_waves = (np_out + kTile - 1) / kTile;
-  int s = (4096 + out_waves - 1) / out_waves;
+  int s = (BDRS_TARGET_WAVES + out_waves - 1) / out_waves;
   const int max_s = (ntiles_in + 3) / 4;
   if (s > max_s) s = max_s;
   if (s < 1) s = 1;
-  return s;
+  const int tps = (ntiles_in + s - 1) / s;
+  return (ntiles_in + tps - 1) / tps;  // splits that own at least one tile
 }
 
 hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int splits, double eps_arg) {
@@ -513,8 +526,7 @@ hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int split
   dim3 grid(out.np / kBlock, splits);
 #define BDRS_SWEEP(DD, CC)                                                                          \
   hipLaunchKernelGGL((k_sweep<DD, CC>), grid, dim3(kBlock), 0, c.stream, out.abs, out.np, in.off,  \
-                     in.hdr, in.A, in.Amax, in.ntiles, tps, c.part.M, c.part.S, c.part.N, c.ctrl, \
-                     eps_arg)
+                     in.hdr, in.A, in.Amax, in.ntiles, tps, c.part.rec, c.ctrl, eps_arg)
   switch (c.dim * 2 + (cert ? 1 : 0)) {
     case 2: BDRS_SWEEP(1, false); break;
     case 3: BDRS_SWEEP(1, true); break;
@@ -530,8 +542,9 @@ hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int split
 
 hipError_t launch_finish(const LaunchCtx& c, bool transpose, FinishKind kind, int splits, double eps_arg,
                          double* lse_out) {
+  // one wavefront per block (one tile of outputs), so the O(n) epilogue spreads over all CUs
   const SideDev& out = transpose ? c.cols : c.rows;
-  hipLaunchKernelGGL(k_finish, dim3(out.np / kBlock), dim3(kBlock), 0, c.stream, c, transpose ? 1 : 0,
+  hipLaunchKernelGGL(k_finish, dim3(out.ntiles), dim3(kTile), 0, c.stream, c, transpose ? 1 : 0,
                      (int)kind, splits, eps_arg, lse_out);
   return hipGetLastError();
 }
