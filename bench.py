@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Gentries/s of fused LSE sweeps + time-to-1% rel. gap; p50/p99 serve latency"
-ETA = 1.0            # initial temperature of the 128x128 workload
+ETA = 0.1            # initial temperature of the grid workloads (tuning: see the design doc)
 CERT_EVERY = 50
 CU, LANES, CLK = 256, 64, 2.4e9
 EXP_SLOTS = 2        # v_exp_f32 issues at half the FMA rate on gfx950
@@ -58,6 +58,138 @@ def cpu_baseline(prob, seconds: float = 12.0) -> dict:
                       f"({entries:.3g} entries, {dt:.1f} s, numpy FP64, one thread)"}
 
 
+def batch_mode(args) -> int:
+    """64 grid problems with sides drawn from {32, 64, 128, 256} (seed 41), each
+    solved to a 1% relative gap: one after another with bdrs_solve, then all at
+    once with bdrs_batch_solve (captured 50-iteration blocks).  Solver set-up
+    is outside both timed regions; results must agree bit for bit."""
+    import numpy as np
+    import torch
+    from paper_2609_33814_amd import bdrs, inputs
+    dev = torch.device("cuda:0")
+    sides = inputs.batch_sides()
+    probs = [inputs.batch_problem(p, s) for p, s in enumerate(sides)]
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    data = [(t(p.x, torch.float32), t(p.y, torch.float32), t(p.r, torch.float64), t(p.c, torch.float64),
+             p.cost_scale) for p in probs]
+    cap, tau = 40000, 0.01
+    print(f"[bench] batch of {len(probs)} grids, sides {sorted(set(sides))}, eta={ETA}", flush=True)
+    # warm-up of every kernel variant
+    w = bdrs.Solver(*data[0][:4], data[0][4], eta=ETA)
+    w.solve(tau, 100, CERT_EVERY)
+    bdrs.batch_solve([w], tau, 100, CERT_EVERY)
+    w.close()
+    seq_t, seq = 0.0, []
+    for i, d in enumerate(data):
+        sv = bdrs.Solver(*d[:4], d[4], eta=ETA)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ok, ce = sv.solve(tau, cap, CERT_EVERY)
+        torch.cuda.synchronize()
+        seq_t += time.perf_counter() - t0
+        seq.append((ok, ce))
+        sv.close()
+    print(f"[bench] sequential: {seq_t:.2f} s", flush=True)
+    svs = [bdrs.Solver(*d[:4], d[4], eta=ETA) for d in data]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, certs, sts = bdrs.batch_solve(svs, tau, cap, CERT_EVERY, use_graph=True)
+    torch.cuda.synchronize()
+    bat_t = time.perf_counter() - t0
+    same = all(c["k"] == s[1]["k"] and c["U"] == s[1]["U"] and c["L"] == s[1]["L"] for c, s in zip(certs, seq))
+    reached = sum(1 for x in sts if x == bdrs.OK)
+    entries = sum(2.0 * p.m * p.n * (c["k"] + 1) for p, c in zip(probs, certs))
+    line = {
+        "metric": "makespan of 64 uneven grid OT solves to 1% relative gap", "value": round(bat_t, 3),
+        "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "64 grid histogram pairs, sides from {32,64,128,256} (seed 41), "
+                               "seeds (4100+2p, 4101+2p)", "eta": ETA, "lambda": 1.0,
+                   "cert_every": CERT_EVERY, "cap": cap},
+        "sequential_s": round(seq_t, 3), "speedup_vs_sequential": round(seq_t / bat_t, 4),
+        "batched_gentries_per_s": round(entries / bat_t / 1e9, 1),
+        "sequential_gentries_per_s": round(entries / seq_t / 1e9, 1),
+        "reached": reached, "bitwise_equal_alone_vs_batched": bool(same),
+        "iterations": {str(s): sorted(set(c["k"] + 1 for c, sd in zip(certs, sides) if sd == s))
+                       for s in sorted(set(sides))},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def serve_mode(args) -> int:
+    """Poisson arrivals of grid OT requests (sides from {32, 64, 128}, drawn with
+    seed 52; inter-arrival gaps with seed 51; request q seeds (5100+2q, 5101+2q)),
+    each stopped at a 1% relative gap.  The arrival rate is `load` times the
+    sequential capacity measured on a sample.  The same arrival schedule is
+    served twice: one request at a time (FIFO) and with continuous batching
+    (up to 32 running requests in a 1 GiB pool)."""
+    import threading
+    import numpy as np
+    import torch
+    from paper_2609_33814_amd import bdrs, inputs
+    n_req = args.requests
+    menu = [32, 64, 128]
+    sides = [menu[i] for i in np.random.default_rng(52).integers(0, len(menu), n_req)]
+    probs = [inputs.grid_problem(s, 5100 + 2 * q, 5101 + 2 * q) for q, s in enumerate(sides)]
+    tau, cap, block, pool = 0.01, 20000, CERT_EVERY, 1 << 30
+    print(f"[bench] serve: {n_req} requests, sides {menu}, eta={ETA}, pool {pool >> 20} MiB", flush=True)
+
+    # sequential capacity from a sample of requests served alone
+    calib = bdrs.Server(pool, 1, block)
+    sample = probs[: min(16, n_req)]
+    t0 = time.perf_counter()
+    for p in sample:
+        calib.wait(calib.submit(p, eta=ETA, tau=tau, max_iters=cap))
+    mean_s = (time.perf_counter() - t0) / len(sample)
+    calib.close()
+    rate = args.load / mean_s
+    gaps = np.random.default_rng(51).exponential(1.0 / rate, n_req)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    print(f"[bench] sequential capacity {1 / mean_s:.2f} solves/s; arrival rate {rate:.2f}/s", flush=True)
+
+    def run(max_slots):
+        srv = bdrs.Server(pool, max_slots, block)
+        tickets = [None] * n_req
+        start = time.perf_counter()
+
+        def feeder():
+            for q in range(n_req):
+                delay = arrivals[q] - (time.perf_counter() - start)
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[q] = srv.submit(probs[q], eta=ETA, tau=tau, max_iters=cap)
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        res = [srv.wait(t) for t in tickets]
+        srv.close()
+        lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+        span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+        ok = sum(1 for r in res if r["status"] == bdrs.OK)
+        return dict(p50_s=round(float(np.percentile(lat, 50)), 4), p99_s=round(float(np.percentile(lat, 99)), 4),
+                    mean_s=round(float(lat.mean()), 4), solves_per_s=round(n_req / span, 3), reached=ok), res
+
+    fifo, res_f = run(1)
+    print(f"[bench] FIFO one at a time: {fifo}", flush=True)
+    cont, res_c = run(32)
+    print(f"[bench] continuous batching: {cont}", flush=True)
+    same = all(a["cert"]["k"] == b["cert"]["k"] and a["cert"]["U"] == b["cert"]["U"] for a, b in zip(res_f, res_c))
+    line = {
+        "metric": "p50/p99 latency of OT solve requests to 1% relative gap (Poisson arrivals)",
+        "value": cont["p99_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{n_req} grid requests, sides from {menu} (seed 52), arrivals Exp (seed 51) at "
+                               f"{args.load} x sequential capacity", "eta": ETA, "lambda": 1.0,
+                   "block_iters": block, "pool_MiB": pool >> 20, "max_slots": 32},
+        "continuous_batching": cont, "fifo_sequential": fifo,
+        "p99_speedup": round(fifo["p99_s"] / cont["p99_s"], 3),
+        "results_equal_fifo_vs_batched": bool(same),
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +199,12 @@ def main() -> int:
     ap.add_argument("--no-ttg", action="store_true", help="skip the time-to-1%% runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--ttg-cap", type=int, default=20000)
+    ap.add_argument("--mode", choices=("sweep", "batch", "serve"), default="sweep",
+                    help="sweep: the headline line (default); batch: 64 uneven grid problems, "
+                         "sequential solves vs one batched solve, to a 1%% gap; serve: Poisson "
+                         "arrivals, FIFO one-at-a-time vs continuous batching")
+    ap.add_argument("--requests", type=int, default=96)
+    ap.add_argument("--load", type=float, default=0.8, help="arrival rate / sequential capacity")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (known bytes) so that "
                          "HBM traffic counters can be scaled")
@@ -81,6 +219,10 @@ def main() -> int:
     from paper_2609_33814_amd import bdrs, inputs
 
     dev = torch.device("cuda:0")
+    if args.mode == "batch":
+        return batch_mode(args)
+    if args.mode == "serve":
+        return serve_mode(args)
     prob = inputs.c2_problem()
     t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     X, Y = t(prob.x, torch.float32), t(prob.y, torch.float32)

@@ -179,6 +179,91 @@ BDRS_API bdrs_status bdrs_set_state(bdrs_solver s, const double *log_alpha,
 BDRS_API bdrs_status bdrs_lse(bdrs_solver s, int32_t transpose, double eps,
                      const double *w, double *out);
 
+/*
+ * Batched solving (many independent problems in one set of launches).
+ * The problems are solver objects from bdrs_create (each with its own
+ * workspace), all with the same dim, all at an iteration count that is a
+ * multiple of cert_every (fresh solvers are at 0).  Every phase of an
+ * iteration (row sweep, row epilogue, column sweep, column epilogue) runs as
+ * ONE launch over a work list of (problem, block of outputs, split) items of
+ * all active problems; a block of cert_every iterations ends with the fused
+ * certificate of every active problem and one readback.  A problem whose
+ * certificate meets the target (the same rule as bdrs_solve) or that reaches
+ * max_iters retires at that block boundary; the others go on.  Each problem's
+ * arithmetic is the same as when it is solved alone with bdrs_solve, so its
+ * results are bitwise equal.
+ * With use_graph != 0 one block of iterations is captured as a hipGraph
+ * (on a private stream) and replayed, and captured again only when the set
+ * of active problems changes.
+ *   workspace   device memory of bdrs_batch_workspace_size() bytes (256-byte
+ *               aligned) for descriptors, work lists and certificate records
+ *   max_iters   per problem, a positive multiple of cert_every
+ *   outs        host array of count certificates (the last of each problem)
+ *   statuses    host array of count statuses (BDRS_OK: target met,
+ *               BDRS_NOT_CONVERGED: cap reached, BDRS_E_NUMERIC)
+ * Synchronous.  Returns BDRS_OK if every problem met the target,
+ * BDRS_NOT_CONVERGED if some hit the cap, an error otherwise. */
+BDRS_API bdrs_status bdrs_batch_workspace_size(const bdrs_solver *solvers, int32_t count,
+                                               size_t *bytes);
+BDRS_API bdrs_status bdrs_batch_solve(const bdrs_solver *solvers, int32_t count, void *workspace,
+                                      size_t workspace_bytes, double tau, int32_t tau_relative,
+                                      int32_t max_iters, int32_t cert_every, int32_t use_graph,
+                                      bdrs_cert *outs, int32_t *statuses);
+
+/*
+ * Solve server: continuous batching of independent OT solves on one GPU.
+ * The server owns a device memory pool given by the caller (the "HBM
+ * budget"); every admitted request gets its workspace (bdrs_workspace_size of
+ * its sizes) from the pool.  A worker thread admits queued requests in
+ * arrival order whenever a slot and pool memory are free, runs blocks of
+ * block_iters iterations of all running requests together (one launch per
+ * phase, as in bdrs_batch_solve), evaluates each request's certificate at
+ * the end of every block, and retires a request when its stopping rule holds
+ * (same rule as bdrs_solve with cert_every = block_iters) or max_iters is
+ * reached, releasing its memory for the next request.  A request's result is
+ * bitwise the same as solving it alone with bdrs_solve.
+ */
+typedef struct bdrs_server_* bdrs_server;
+
+/* One solve request.  Inputs are HOST arrays, copied by bdrs_server_submit. */
+typedef struct {
+  int32_t m, n, dim;
+  const float *x, *y;          /* host, row-major m x dim / n x dim */
+  const double *r, *c;         /* host marginals (as in bdrs_params) */
+  double cost_scale, eta, lambda, omega;
+  double tau;                  /* stop when the (relative) best gap <= tau */
+  int32_t tau_relative;
+  int32_t max_iters;           /* positive multiple of the server's block_iters */
+} bdrs_request;
+
+typedef struct {
+  int32_t state;               /* 0 queued, 1 running, 2 done */
+  int32_t status;              /* when done: BDRS_OK, BDRS_NOT_CONVERGED or an error */
+  bdrs_cert cert;              /* the last certificate (when done) */
+  double t_submit, t_admit, t_done;  /* seconds on the server clock (bdrs_server_now) */
+} bdrs_result;
+
+/* pool: device memory (256-byte aligned) of pool_bytes, owned by the caller
+ * until bdrs_server_destroy.  max_slots >= 1 requests run concurrently.
+ * block_iters >= 1 iterations per block.  Starts the worker thread. */
+BDRS_API bdrs_status bdrs_server_create(void *pool, size_t pool_bytes, int32_t max_slots,
+                                        int32_t block_iters, bdrs_server *out);
+/* Validates and copies a request; thread-safe.  BDRS_E_NOMEM if its
+ * workspace can never fit the pool.  *ticket identifies the request. */
+BDRS_API bdrs_status bdrs_server_submit(bdrs_server s, const bdrs_request *req, uint64_t *ticket);
+/* Non-blocking state of a request. */
+BDRS_API bdrs_status bdrs_server_poll(bdrs_server s, uint64_t ticket, bdrs_result *out);
+/* Blocks until the request is done (or the server stops). */
+BDRS_API bdrs_status bdrs_server_wait(bdrs_server s, uint64_t ticket, bdrs_result *out);
+/* Counts: running and queued requests, pool bytes in use. */
+BDRS_API bdrs_status bdrs_server_stats(bdrs_server s, int32_t *running, int32_t *queued,
+                                       size_t *pool_used);
+/* Seconds since the server was created (the clock of bdrs_result). */
+BDRS_API bdrs_status bdrs_server_now(bdrs_server s, double *t);
+/* Stops the worker after its current block; requests not finished by then
+ * end with BDRS_E_STATE.  Frees host memory; the pool stays the caller's. */
+BDRS_API bdrs_status bdrs_server_destroy(bdrs_server s);
+
 /* Kernel timing for measurement.  enable != 0 brackets every LSE sweep
  * kernel this solver launches from then on with a pair of HIP events on the
  * solver's stream and clears the totals; enable == 0 stops recording.

@@ -19,7 +19,9 @@ F_REPAIR = 1
 EXPORTS = [
     "bdrs_workspace_size", "bdrs_create", "bdrs_step", "bdrs_certificate", "bdrs_solve",
     "bdrs_get_state", "bdrs_set_state", "bdrs_lse", "bdrs_destroy", "bdrs_last_error",
-    "bdrs_version", "bdrs_profile", "bdrs_profile_read",
+    "bdrs_version", "bdrs_profile", "bdrs_profile_read", "bdrs_batch_workspace_size",
+    "bdrs_batch_solve", "bdrs_server_create", "bdrs_server_submit", "bdrs_server_poll",
+    "bdrs_server_wait", "bdrs_server_stats", "bdrs_server_now", "bdrs_server_destroy",
 ]
 
 
@@ -48,6 +50,28 @@ class Cert(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("dim", ctypes.c_int32),
+        ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+        ("r", ctypes.c_void_p), ("c", ctypes.c_void_p),
+        ("cost_scale", ctypes.c_double), ("eta", ctypes.c_double),
+        ("lambda_", ctypes.c_double), ("omega", ctypes.c_double),
+        ("tau", ctypes.c_double), ("tau_relative", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("state", ctypes.c_int32), ("status", ctypes.c_int32), ("cert", Cert),
+        ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return dict(state=self.state, status=self.status, cert=self.cert.as_dict(),
+                    t_submit=self.t_submit, t_admit=self.t_admit, t_done=self.t_done)
 
 
 class BdrsError(RuntimeError):
@@ -79,7 +103,18 @@ def lib() -> ctypes.CDLL:
         L.bdrs_lse.argtypes = [vp, ctypes.c_int32, ctypes.c_double, vp, vp]
         L.bdrs_destroy.argtypes = [vp]
         L.bdrs_profile.argtypes = [vp, ctypes.c_int32]
+        L.bdrs_batch_workspace_size.argtypes = [P(vp), ctypes.c_int32, P(ctypes.c_size_t)]
+        L.bdrs_batch_solve.argtypes = [P(vp), ctypes.c_int32, vp, ctypes.c_size_t, ctypes.c_double,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       P(Cert), P(ctypes.c_int32)]
         L.bdrs_profile_read.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_double), P(ctypes.c_double)]
+        L.bdrs_server_create.argtypes = [vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, P(vp)]
+        L.bdrs_server_submit.argtypes = [vp, P(Request), P(ctypes.c_uint64)]
+        L.bdrs_server_poll.argtypes = [vp, ctypes.c_uint64, P(Result)]
+        L.bdrs_server_wait.argtypes = [vp, ctypes.c_uint64, P(Result)]
+        L.bdrs_server_stats.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_size_t)]
+        L.bdrs_server_now.argtypes = [vp, P(ctypes.c_double)]
+        L.bdrs_server_destroy.argtypes = [vp]
         L.bdrs_last_error.restype = ctypes.c_char_p
         L.bdrs_version.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -198,6 +233,89 @@ class Solver:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().bdrs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_solve(solvers, tau: float, max_iters: int, cert_every: int, relative: bool = True,
+                use_graph: bool = True):
+    """Solves several Solver objects together (bdrs_batch_solve).
+
+    Returns (status, [cert dict per solver], [status per solver]).
+    """
+    import torch
+    n = len(solvers)
+    arr = (ctypes.c_void_p * n)(*[s.handle.value for s in solvers])
+    size = ctypes.c_size_t()
+    check(lib().bdrs_batch_workspace_size(arr, n, ctypes.byref(size)))
+    dev = solvers[0]._inputs[0].device
+    ws = torch.empty(size.value + 256, dtype=torch.uint8, device=dev)
+    ptr = (ws.data_ptr() + 255) // 256 * 256
+    outs = (Cert * n)()
+    sts = (ctypes.c_int32 * n)()
+    st = lib().bdrs_batch_solve(arr, n, ptr, size.value, float(tau), 1 if relative else 0,
+                                int(max_iters), int(cert_every), 1 if use_graph else 0, outs, sts)
+    check(st, allow=(OK, NOT_CONVERGED))
+    del ws
+    return st, [o.as_dict() for o in outs], list(sts)
+
+
+class Server:
+    """Continuous-batching solve server over a device memory pool (bdrs_server_*)."""
+
+    def __init__(self, pool_bytes: int, max_slots: int, block_iters: int = 50, device=None):
+        import torch
+        dev = device if device is not None else torch.device("cuda:0")
+        self._pool = torch.empty(pool_bytes + 256, dtype=torch.uint8, device=dev)
+        ptr = (self._pool.data_ptr() + 255) // 256 * 256
+        torch.cuda.synchronize(dev)
+        h = ctypes.c_void_p()
+        check(lib().bdrs_server_create(ptr, pool_bytes, int(max_slots), int(block_iters), ctypes.byref(h)))
+        self._h = h
+        self.block_iters = block_iters
+
+    def submit(self, prob, eta=1.0, lam=1.0, omega=1.0, tau=0.01, relative=True, max_iters=20000) -> int:
+        """prob: an inputs.Problem (host arrays).  Returns the ticket."""
+        import numpy as np
+        x = np.ascontiguousarray(prob.x, dtype=np.float32)
+        y = np.ascontiguousarray(prob.y, dtype=np.float32)
+        r = np.ascontiguousarray(prob.r, dtype=np.float64)
+        c = np.ascontiguousarray(prob.c, dtype=np.float64)
+        req = Request(x.shape[0], y.shape[0], x.shape[1], x.ctypes.data, y.ctypes.data, r.ctypes.data,
+                      c.ctypes.data, float(prob.cost_scale), float(eta), float(lam), float(omega),
+                      float(tau), 1 if relative else 0, int(max_iters))
+        t = ctypes.c_uint64()
+        check(lib().bdrs_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> dict:
+        out = Result()
+        check(lib().bdrs_server_poll(self._h, ticket, ctypes.byref(out)))
+        return out.as_dict()
+
+    def wait(self, ticket: int) -> dict:
+        out = Result()
+        check(lib().bdrs_server_wait(self._h, ticket, ctypes.byref(out)))
+        return out.as_dict()
+
+    def stats(self) -> dict:
+        a, q, u = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        check(lib().bdrs_server_stats(self._h, ctypes.byref(a), ctypes.byref(q), ctypes.byref(u)))
+        return dict(running=a.value, queued=q.value, pool_used=u.value)
+
+    def now(self) -> float:
+        t = ctypes.c_double()
+        check(lib().bdrs_server_now(self._h, ctypes.byref(t)))
+        return t.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().bdrs_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -5,8 +5,7 @@
 // (Morton order, so that each 64-point tile is spatially compact), and the
 // iteration / certificate loop of Algorithm 1 with the best-bound stopping
 // rule.
-#include "bdrs_internal.h"
-#include "../../include/bdrs.h"
+#include "bdrs_host.h"
 
 #include <algorithm>
 #include <cmath>
@@ -19,7 +18,7 @@
 
 using namespace bdrs;
 
-namespace {
+namespace bdrs_host {
 
 thread_local std::string g_err;
 
@@ -40,12 +39,7 @@ bdrs_status fail(bdrs_status st, const char* fmt, ...) {
       return fail(BDRS_E_DEVICE, "HIP error %s in %s", hipGetErrorString(e_), #expr);     \
   } while (0)
 
-constexpr size_t kAlign = 256;
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-struct SideShape {
-  int count, ntiles, np;
-};
 
 SideShape side_shape(int count) {
   SideShape s;
@@ -55,19 +49,6 @@ SideShape side_shape(int count) {
   return s;
 }
 
-// Offsets of every sub-buffer inside the workspace.
-struct Layout {
-  SideShape R, C;
-  int splits_row, splits_col, splits_max;
-  int cert_blocks;
-  size_t total;
-  // offsets
-  size_t ctrl;
-  size_t r_abs, r_off, r_hdr, r_A, r_Amax, r_perm, r_marg, r_logm;
-  size_t c_abs, c_off, c_hdr, c_A, c_Amax, c_perm, c_marg, c_logm;
-  size_t la, lah, lb1, lb2, lbh, lt0, lt1, mu, logs, pvec;
-  size_t part, cert_part, cert_out;
-};
 
 Layout make_layout(int m, int n, int dim) {
   Layout L{};
@@ -247,26 +228,7 @@ void build_side(const std::vector<float>& pts, const std::vector<double>& w, int
   }
 }
 
-}  // namespace
 
-struct bdrs_solver_ {
-  bdrs_params prm;
-  Layout L;
-  LaunchCtx ctx;
-  long long k = 0;          // finished iterations, refreshed from Ctrl::k by sync_k (the
-                            // device counter is the truth: captured graphs advance it)
-  double U_best = INFINITY, L_best = -INFINITY;
-  long long kU = -1, kL = -1;
-  bool packed_rows = false; // rows.A holds log alpha-hat of iteration k-1
-  // sweep timing (bdrs_profile)
-  bool prof = false;
-  std::vector<hipEvent_t> ev_pool;  // created on demand, reused after each read
-  size_t ev_used = 0;
-  double prof_entries = 0.0;
-  long long prof_sweeps = 0;
-};
-
-namespace {
 
 void fill_ctx(bdrs_solver s) {
   const Layout& L = s->L;
@@ -274,6 +236,8 @@ void fill_ctx(bdrs_solver s) {
   LaunchCtx& c = s->ctx;
   c.stream = (hipStream_t)s->prm.stream;
   c.dim = s->prm.dim;
+  c.splits_row = L.splits_row;
+  c.splits_col = L.splits_col;
   c.ctrl = (Ctrl*)(base + L.ctrl);
   auto side = [&](SideDev& sd, const SideShape& sh, size_t abs, size_t off, size_t hdr, size_t A, size_t Amax,
                   size_t perm, size_t marg, size_t logm) {
@@ -374,10 +338,8 @@ bdrs_status repack(bdrs_solver s) {
   return BDRS_OK;
 }
 
-bdrs_status read_cert(bdrs_solver s, bool repair, bdrs_cert* out) {
-  double h[kCertSlots];
-  HIPCHK(hipMemcpyAsync(h, s->ctx.cert_out, sizeof h, hipMemcpyDeviceToHost, s->ctx.stream));
-  HIPCHK(hipStreamSynchronize(s->ctx.stream));
+// certificate record (kCertSlots doubles, host) -> bdrs_cert, updating the best bounds
+bdrs_status cert_from_record(bdrs_solver s, const double* h, bool repair, bdrs_cert* out) {
   bdrs_cert ce;
   ce.k = (int64_t)h[0];
   ce.eps = h[1];
@@ -409,6 +371,13 @@ bdrs_status read_cert(bdrs_solver s, bool repair, bdrs_cert* out) {
   return BDRS_OK;
 }
 
+bdrs_status read_cert(bdrs_solver s, bool repair, bdrs_cert* out) {
+  double h[kCertSlots];
+  HIPCHK(hipMemcpyAsync(h, s->ctx.cert_out, sizeof h, hipMemcpyDeviceToHost, s->ctx.stream));
+  HIPCHK(hipStreamSynchronize(s->ctx.stream));
+  return cert_from_record(s, h, repair, out);
+}
+
 bdrs_status enqueue_repair(bdrs_solver s) {
   const LaunchCtx& c = s->ctx;
   hipError_t e;
@@ -422,9 +391,238 @@ bdrs_status enqueue_repair(bdrs_solver s) {
   return BDRS_OK;
 }
 
-}  // namespace
+size_t row_sweep_items(const bdrs_solver s) { return (size_t)(s->L.R.np / kBlock) * s->L.splits_row; }
+size_t col_sweep_items(const bdrs_solver s) { return (size_t)(s->L.C.np / kBlock) * s->L.splits_col; }
+
+BatchLayout batch_layout(const std::vector<bdrs_solver>& sv) {
+  BatchLayout B{};
+  for (bdrs_solver s : sv) {
+    B.n_rs += row_sweep_items(s);
+    B.n_cs += col_sweep_items(s);
+    B.n_rf += s->L.R.ntiles;
+    B.n_cf += s->L.C.ntiles;
+    B.n_ce += s->L.cert_blocks;
+  }
+  const size_t count = sv.size();
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  B.descs = take(sizeof(LaunchCtx) * count);
+  B.items_rs = take(sizeof(BatchItem) * B.n_rs);
+  B.items_cs = take(sizeof(BatchItem) * B.n_cs);
+  B.items_rf = take(sizeof(BatchItem) * B.n_rf);
+  B.items_cf = take(sizeof(BatchItem) * B.n_cf);
+  B.items_ce = take(sizeof(BatchItem) * B.n_ce);
+  B.probs = take(sizeof(int) * count);
+  B.records = take(sizeof(double) * kCertSlots * count);
+  B.total = o;
+  return B;
+}
+
+size_t BatchEngine::bytes_for(const std::vector<bdrs_solver>& members) { return batch_layout(members).total; }
+
+BatchEngine::~BatchEngine() {
+  if (exec_) hipGraphExecDestroy(exec_);
+}
+
+hipError_t BatchEngine::bind(const std::vector<bdrs_solver>& members, char* ws, int block_iters, bool use_graph,
+                             hipStream_t st) {
+  if (exec_) {
+    hipGraphExecDestroy(exec_);
+    exec_ = nullptr;
+  }
+  members_ = members;
+  ws_ = ws;
+  st_ = st;
+  iters_ = block_iters;
+  B_ = batch_layout(members_);
+  dim_ = members_.empty() ? 0 : members_[0]->prm.dim;
+  std::vector<LaunchCtx> descs;
+  std::vector<BatchItem> rs, cs, rf, cf, ce;
+  std::vector<int> probs;
+  for (int p = 0; p < (int)members_.size(); ++p) {
+    const bdrs_solver s = members_[p];
+    descs.push_back(s->ctx);
+    for (int sp = 0; sp < s->L.splits_row; ++sp)
+      for (int b = 0; b < s->L.R.np / kBlock; ++b) rs.push_back({p, b, sp, 0});
+    for (int sp = 0; sp < s->L.splits_col; ++sp)
+      for (int b = 0; b < s->L.C.np / kBlock; ++b) cs.push_back({p, b, sp, 0});
+    for (int t = 0; t < s->L.R.ntiles; ++t) rf.push_back({p, t, 0, 0});
+    for (int t = 0; t < s->L.C.ntiles; ++t) cf.push_back({p, t, 0, 0});
+    for (int b = 0; b < s->L.cert_blocks; ++b) ce.push_back({p, b, 0, 0});
+    probs.push_back(p);
+  }
+  nrs_ = (int)rs.size();
+  ncs_ = (int)cs.size();
+  nrf_ = (int)rf.size();
+  ncf_ = (int)cf.size();
+  nce_ = (int)ce.size();
+  hipError_t r = hipSuccess;
+  auto up = [&](size_t off, const void* src, size_t bytes) {
+    if (r == hipSuccess && bytes) r = hipMemcpyAsync(ws_ + off, src, bytes, hipMemcpyHostToDevice, st_);
+  };
+  up(B_.descs, descs.data(), descs.size() * sizeof(LaunchCtx));
+  up(B_.items_rs, rs.data(), rs.size() * sizeof(BatchItem));
+  up(B_.items_cs, cs.data(), cs.size() * sizeof(BatchItem));
+  up(B_.items_rf, rf.data(), rf.size() * sizeof(BatchItem));
+  up(B_.items_cf, cf.data(), cf.size() * sizeof(BatchItem));
+  up(B_.items_ce, ce.data(), ce.size() * sizeof(BatchItem));
+  up(B_.probs, probs.data(), probs.size() * sizeof(int));
+  if (r == hipSuccess) r = hipStreamSynchronize(st_);  // host vectors go out of scope
+  if (r == hipSuccess && use_graph && !members_.empty()) {
+    hipGraph_t g = nullptr;
+    r = hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal);
+    if (r == hipSuccess) {
+      const hipError_t r2 = enqueue(st_);
+      r = hipStreamEndCapture(st_, &g);
+      if (r == hipSuccess) r = r2;
+    }
+    if (r == hipSuccess) r = hipGraphInstantiate(&exec_, g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+  }
+  return r;
+}
+
+// one block of iters_ iterations (the last with the fused certificate) plus
+// the certificate reductions of every member
+hipError_t BatchEngine::enqueue(hipStream_t st) {
+  const LaunchCtx* descs = (const LaunchCtx*)(ws_ + B_.descs);
+  const BatchItem* rs = (const BatchItem*)(ws_ + B_.items_rs);
+  const BatchItem* cs = (const BatchItem*)(ws_ + B_.items_cs);
+  const BatchItem* rf = (const BatchItem*)(ws_ + B_.items_rf);
+  const BatchItem* cf = (const BatchItem*)(ws_ + B_.items_cf);
+  const BatchItem* ce = (const BatchItem*)(ws_ + B_.items_ce);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < iters_ && e == hipSuccess; ++i) {
+    const bool cert = (i == iters_ - 1);
+    e = launch_sweep_batch(rs, nrs_, descs, dim_, false, false, st);
+    if (e == hipSuccess) e = launch_finish_batch(rf, nrf_, descs, false, kFinishRow, st);
+    if (e == hipSuccess) e = launch_sweep_batch(cs, ncs_, descs, dim_, true, cert, st);
+    if (e == hipSuccess) e = launch_finish_batch(cf, ncf_, descs, true, cert ? kFinishColCert : kFinishCol, st);
+  }
+  if (e == hipSuccess)
+    e = launch_cert_batch(ce, nce_, (const int*)(ws_ + B_.probs), (int)members_.size(), descs,
+                          (double*)(ws_ + B_.records), st);
+  return e;
+}
+
+hipError_t BatchEngine::run_block() {
+  if (members_.empty()) return hipSuccess;
+  return exec_ ? hipGraphLaunch(exec_, st_) : enqueue(st_);
+}
+
+hipError_t BatchEngine::read_records(std::vector<double>& rec) {
+  rec.resize(members_.size() * kCertSlots);
+  if (rec.empty()) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(rec.data(), ws_ + B_.records, rec.size() * sizeof(double), hipMemcpyDeviceToHost, st_);
+  if (e == hipSuccess) e = hipStreamSynchronize(st_);
+  return e;
+}
+
+bdrs_status check_batch(const bdrs_solver* sv, int count) {
+  if (!sv) return fail(BDRS_E_INVALID, "solvers is NULL");
+  if (count < 1) return fail(BDRS_E_INVALID, "count must be >= 1");
+  for (int i = 0; i < count; ++i) {
+    if (!sv[i]) return fail(BDRS_E_INVALID, "solvers[%d] is NULL", i);
+    if (sv[i]->prm.dim != sv[0]->prm.dim) return fail(BDRS_E_INVALID, "solvers[%d] has another dim", i);
+    for (int j = 0; j < i; ++j)
+      if (sv[j] == sv[i]) return fail(BDRS_E_INVALID, "solvers[%d] is listed twice", i);
+  }
+  return BDRS_OK;
+}
+
+}  // namespace bdrs_host
+
+using namespace bdrs_host;
 
 extern "C" {
+
+bdrs_status bdrs_batch_workspace_size(const bdrs_solver* solvers, int32_t count, size_t* bytes) {
+  bdrs_status st = check_batch(solvers, count);
+  if (st != BDRS_OK) return st;
+  if (!bytes) return fail(BDRS_E_INVALID, "bytes is NULL");
+  *bytes = BatchEngine::bytes_for(std::vector<bdrs_solver>(solvers, solvers + count));
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_batch_solve(const bdrs_solver* solvers, int32_t count, void* workspace, size_t workspace_bytes,
+                             double tau, int32_t tau_relative, int32_t max_iters, int32_t cert_every,
+                             int32_t use_graph, bdrs_cert* outs, int32_t* statuses) {
+  bdrs_status st = check_batch(solvers, count);
+  if (st != BDRS_OK) return st;
+  if (!outs || !statuses) return fail(BDRS_E_INVALID, "outs and statuses are required");
+  if (!(tau >= 0 && std::isfinite(tau))) return fail(BDRS_E_INVALID, "tau must be finite and >= 0");
+  if (cert_every < 1) return fail(BDRS_E_INVALID, "cert_every must be >= 1");
+  if (max_iters < 1 || max_iters % cert_every)
+    return fail(BDRS_E_INVALID, "max_iters must be a positive multiple of cert_every");
+  if (!workspace || ((uintptr_t)workspace) % kAlign)
+    return fail(BDRS_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+  std::vector<bdrs_solver> all(solvers, solvers + count);
+  const size_t need = BatchEngine::bytes_for(all);
+  if (workspace_bytes < need)
+    return fail(BDRS_E_NOMEM, "batch workspace too small: %zu bytes given, %zu needed", workspace_bytes, need);
+  for (int i = 0; i < count; ++i) {
+    if ((st = sync_k(solvers[i])) != BDRS_OK) return st;
+    if (solvers[i]->k % cert_every)
+      return fail(BDRS_E_STATE, "solvers[%d] is at iteration %lld, not a multiple of cert_every", i, solvers[i]->k);
+    if (solvers[i]->prm.flags & BDRS_F_REPAIR)
+      return fail(BDRS_E_INVALID, "solvers[%d]: BDRS_F_REPAIR is not supported in batches", i);
+  }
+  hipStream_t st_b = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&st_b, hipStreamNonBlocking));
+  std::vector<int> index(count), done_iters(count, 0);
+  for (int i = 0; i < count; ++i) {
+    index[i] = i;
+    statuses[i] = BDRS_NOT_CONVERGED;
+  }
+  std::vector<int> active = index;
+  bdrs_status result = BDRS_OK;
+  hipError_t e;
+  {
+    BatchEngine eng;
+    e = eng.bind(all, (char*)workspace, cert_every, use_graph != 0, st_b);
+    std::vector<double> rec;
+    while (e == hipSuccess && !active.empty()) {
+      e = eng.run_block();
+      if (e == hipSuccess) e = eng.read_records(rec);
+      if (e != hipSuccess) break;
+      std::vector<int> still;
+      for (size_t q = 0; q < active.size(); ++q) {
+        const int p = active[q];
+        bdrs_solver s = solvers[p];
+        s->k += cert_every;
+        done_iters[p] += cert_every;
+        const bdrs_status cs_st = cert_from_record(s, rec.data() + q * kCertSlots, false, &outs[p]);
+        const double target = tau_relative ? outs[p].rel_gap_best : (outs[p].U_best - outs[p].L_best);
+        if (cs_st != BDRS_OK) {
+          statuses[p] = cs_st;
+          result = cs_st;
+        } else if (target <= tau) {
+          statuses[p] = BDRS_OK;
+        } else if (done_iters[p] >= max_iters) {
+          statuses[p] = BDRS_NOT_CONVERGED;
+          if (result == BDRS_OK) result = BDRS_NOT_CONVERGED;
+        } else {
+          still.push_back(p);
+        }
+      }
+      if (still.size() != active.size()) {
+        active.swap(still);
+        std::vector<bdrs_solver> mem;
+        for (int p : active) mem.push_back(solvers[p]);
+        e = eng.bind(mem, (char*)workspace, cert_every, use_graph != 0, st_b);
+      }
+    }
+  }
+  hipStreamSynchronize(st_b);
+  hipStreamDestroy(st_b);
+  if (e != hipSuccess) return fail(BDRS_E_DEVICE, "HIP error %s in batch solve", hipGetErrorString(e));
+  for (int i = 0; i < count; ++i) solvers[i]->packed_rows = true;
+  return result;
+}
 
 const char* bdrs_last_error(void) { return g_err.c_str(); }
 
@@ -454,6 +652,20 @@ bdrs_status bdrs_create(const bdrs_params* p, bdrs_solver* out) {
   HIPCHK(hipMemcpyAsync(hr.data(), p->r, m * sizeof(double), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipMemcpyAsync(hc.data(), p->c, n * sizeof(double), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
+  return create_from_host(p, hx.data(), hy.data(), hr.data(), hc.data(), out);
+}
+
+}  // extern "C"
+
+namespace bdrs_host {
+
+bdrs_status create_from_host(const bdrs_params* p, const float* px, const float* py, const double* pr,
+                             const double* pc, bdrs_solver* out) {
+  *out = nullptr;
+  const int m = p->m, n = p->n, dim = p->dim;
+  hipStream_t stream = (hipStream_t)p->stream;
+  const std::vector<float> hx(px, px + (size_t)m * dim), hy(py, py + (size_t)n * dim);
+  const std::vector<double> hr(pr, pr + m), hc(pc, pc + n);
 
   // contents: finite coordinates, strictly positive marginals of unit mass (Eq. 1)
   for (size_t i = 0; i < hx.size(); ++i)
@@ -535,6 +747,10 @@ bdrs_status bdrs_create(const bdrs_params* p, bdrs_solver* out) {
   *out = s;
   return BDRS_OK;
 }
+
+}  // namespace bdrs_host
+
+extern "C" {
 
 bdrs_status bdrs_step(bdrs_solver s, int32_t iters) {
   if (!s) return fail(BDRS_E_INVALID, "solver is NULL");

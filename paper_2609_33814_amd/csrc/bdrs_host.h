@@ -1,0 +1,96 @@
+// Internal declarations of the host runtime (shared by the C ABI, the batch
+// engine and the solve server).
+#pragma once
+#include "bdrs_internal.h"
+#include "../../include/bdrs.h"
+
+#include <string>
+#include <vector>
+
+namespace bdrs_host {
+
+using namespace bdrs;
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bdrs_status fail(bdrs_status st, const char* fmt, ...);
+bdrs_status hip_status(hipError_t e, const char* what);
+
+struct SideShape {
+  int count, ntiles, np;
+};
+
+// Offsets of every sub-buffer inside the workspace.
+struct Layout {
+  SideShape R, C;
+  int splits_row, splits_col, splits_max;
+  int cert_blocks;
+  size_t total;
+  // offsets
+  size_t ctrl;
+  size_t r_abs, r_off, r_hdr, r_A, r_Amax, r_perm, r_marg, r_logm;
+  size_t c_abs, c_off, c_hdr, c_A, c_Amax, c_perm, c_marg, c_logm;
+  size_t la, lah, lb1, lb2, lbh, lt0, lt1, mu, logs, pvec;
+  size_t part, cert_part, cert_out;
+};
+
+Layout make_layout(int m, int n, int dim);
+bdrs_status check_sizes(const bdrs_params* p);
+bdrs_status check_params(const bdrs_params* p);
+bdrs_status check_device();
+
+// Builds a solver from host copies of the inputs (contents validated here).
+bdrs_status create_from_host(const bdrs_params* p, const float* hx, const float* hy, const double* hr,
+                             const double* hc, bdrs_solver* out);
+bdrs_status sync_k(bdrs_solver s);
+bdrs_status cert_from_record(bdrs_solver s, const double* rec, bool repair, bdrs_cert* out);
+
+struct BatchLayout {
+  size_t descs, items_rs, items_cs, items_rf, items_cf, items_ce, probs, records, total;
+  size_t n_rs, n_cs, n_rf, n_cf, n_ce;  // item capacities (all problems active)
+};
+
+// Runs blocks of iterations for a set of solvers (same dim) with one launch
+// per phase over work lists of all members.  Device storage: a caller region.
+class BatchEngine {
+ public:
+  static size_t bytes_for(const std::vector<bdrs_solver>& members);
+  // (re)binds the members: uploads descriptors and work lists into `ws`
+  // (at least bytes_for(members) bytes) and, with a graph, captures one block
+  hipError_t bind(const std::vector<bdrs_solver>& members, char* ws, int block_iters, bool use_graph,
+                  hipStream_t st);
+  hipError_t run_block();                               // enqueue one block (+ certificates)
+  hipError_t read_records(std::vector<double>& rec);    // D2H of the members' records, synchronises
+  const std::vector<bdrs_solver>& members() const { return members_; }
+  ~BatchEngine();
+
+ private:
+  hipError_t enqueue(hipStream_t st);
+  std::vector<bdrs_solver> members_;
+  BatchLayout B_{};
+  char* ws_ = nullptr;
+  hipStream_t st_ = nullptr;
+  int dim_ = 0, iters_ = 0;
+  int nrs_ = 0, ncs_ = 0, nrf_ = 0, ncf_ = 0, nce_ = 0;
+  hipGraphExec_t exec_ = nullptr;
+};
+
+}  // namespace bdrs_host
+
+struct bdrs_solver_ {
+  bdrs_params prm;
+  bdrs_host::Layout L;
+  bdrs::LaunchCtx ctx;
+  long long k = 0;          // finished iterations, refreshed from Ctrl::k by sync_k (the
+                            // device counter is the truth: captured graphs advance it)
+  double U_best = INFINITY, L_best = -INFINITY;
+  long long kU = -1, kL = -1;
+  bool packed_rows = false; // rows.A holds log alpha-hat of iteration k-1
+  // sweep timing (bdrs_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;  // created on demand, reused after each read
+  size_t ev_used = 0;
+  double prof_entries = 0.0;
+  long long prof_sweeps = 0;
+};

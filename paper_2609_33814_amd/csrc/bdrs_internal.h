@@ -80,6 +80,7 @@ enum FinishKind {
 struct LaunchCtx {
   hipStream_t stream;
   int dim;
+  int splits_row, splits_col;  // input splits of the row / column sweep
   Ctrl* ctrl;
   SideDev rows, cols;
   StateDev st;
@@ -87,6 +88,12 @@ struct LaunchCtx {
   double* cert_part;   // [cert_blocks][8]
   double* cert_out;    // [kCertSlots]
   int cert_blocks;
+};
+
+// One work item of a batched phase: problem index into the descriptor array,
+// block of outputs (or output tile), and input split (sweeps only).
+struct BatchItem {
+  int prob, blk, split, pad;
 };
 
 // Kernel launchers (bdrs_kernels.hip).  Each returns the launch status.
@@ -101,6 +108,14 @@ hipError_t launch_repair_pack(const LaunchCtx& c);
 hipError_t launch_repair_reduce(const LaunchCtx& c);
 hipError_t launch_scatter(const double* src, const int* perm, int count, double* dst, hipStream_t s);
 hipError_t launch_gather(const double* src, const int* perm, int np, double* dst, hipStream_t s);
+
+// Batched phases over the problems in `descs` (device array of LaunchCtx).
+hipError_t launch_sweep_batch(const BatchItem* items, int nitems, const LaunchCtx* descs, int dim,
+                              bool transpose, bool cert, hipStream_t s);
+hipError_t launch_finish_batch(const BatchItem* items, int nitems, const LaunchCtx* descs, bool transpose,
+                               FinishKind kind, hipStream_t s);
+hipError_t launch_cert_batch(const BatchItem* items, int nitems, const int* probs, int nprobs,
+                             const LaunchCtx* descs, double* records, hipStream_t s);
 
 int choose_splits(int np_out, int ntiles_in);
 

@@ -44,7 +44,8 @@ constexpr double kLog2eD = 1.4426950408889634074;
 constexpr double kLn2D = 0.69314718055994530942;
 constexpr float kThresh = 64.0f;
 
-__device__ __forceinline__ double eps_of(const Ctrl* c, double eps_arg, int kshift) {
+template <typename CtrlPtr>
+__device__ __forceinline__ double eps_of(CtrlPtr c, double eps_arg, int kshift) {
   if (eps_arg > 0.0) return eps_arg;
   return c->eta / (c->lam * (double)(c->k + kshift) + 1.0);  // eta_k = eta / (lambda k + 1)
 }
@@ -66,15 +67,22 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ---------------------------------------------------------------------------
 // Sweep
 // ---------------------------------------------------------------------------
+// Global-address-space views: the tile data is read through these so that
+// uniform reads compile to scalar loads also when the pointers come from a
+// descriptor in memory (batched launches), not only from kernel arguments.
+typedef __attribute__((address_space(1))) const float gfloat;
+typedef __attribute__((address_space(1))) const double gdouble;
+typedef __attribute__((address_space(1))) const Ctrl gctrl;
+
+// One block of 256 outputs (bx) against one split of the input tiles.
 template <int D, bool CERT>
-__global__ __launch_bounds__(kBlock) void k_sweep(
-    const float* __restrict__ out_abs, int np_out,
-    const float* __restrict__ in_off, const float* __restrict__ in_hdr,
-    const float* __restrict__ in_A, const double* __restrict__ in_Amax,
+__device__ __forceinline__ void sweep_block(
+    gfloat* __restrict__ out_abs, int np_out,
+    gfloat* __restrict__ in_off, gfloat* __restrict__ in_hdr,
+    gfloat* __restrict__ in_A, gdouble* __restrict__ in_Amax,
     int ntiles_in, int tps,
-    PartialRec* __restrict__ part, const Ctrl* __restrict__ ctrl, double eps_arg) {
-  const int p = blockIdx.x * kBlock + threadIdx.x;
-  const int split = blockIdx.y;
+    PartialRec* __restrict__ part, gctrl* __restrict__ ctrl, double eps_arg, int bx, int split) {
+  const int p = bx * kBlock + threadIdx.x;
   const int t0 = split * tps;
   const int t1 = min(t0 + tps, ntiles_in);
   const double eps = eps_of(ctrl, eps_arg, 0);
@@ -89,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(
   float S = 0.0f, N = 0.0f;
 
   for (int t = t0; t < t1; ++t) {
-    const float* __restrict__ hdr = in_hdr + (size_t)t * kHdr;
+    gfloat* __restrict__ hdr = in_hdr + (size_t)t * kHdr;
     const double amax = in_Amax[t];
     if (amax == -INFINITY) continue;  // tile carries no mass (masked weights)
     float a[D], B[D], na = 0.0f;
@@ -104,8 +112,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep(
 #pragma unroll
     for (int d = 0; d < D; ++d) bnd = fmaf(fabsf(B[d]), hdr[3 + d], bnd);
 
-    const float* __restrict__ offs = in_off + (size_t)t * D * kTile;
-    const float* __restrict__ Aq = in_A + (size_t)t * kTile;
+    gfloat* __restrict__ offs = in_off + (size_t)t * D * kTile;
+    gfloat* __restrict__ Aq = in_A + (size_t)t * kTile;
 
     if (base + (double)bnd > M + kThresh) {
       // exact maximum of this tile for the lanes whose bound exceeds the window
@@ -161,6 +169,35 @@ __global__ __launch_bounds__(kBlock) void k_sweep(
   rec.S = S;
   rec.N = CERT ? N : 0.0f;
   part[(size_t)split * np_out + p] = rec;
+}
+
+template <int D, bool CERT>
+__global__ __launch_bounds__(kBlock) void k_sweep(
+    const float* __restrict__ out_abs, int np_out,
+    const float* __restrict__ in_off, const float* __restrict__ in_hdr,
+    const float* __restrict__ in_A, const double* __restrict__ in_Amax,
+    int ntiles_in, int tps,
+    PartialRec* __restrict__ part, const Ctrl* __restrict__ ctrl, double eps_arg) {
+  sweep_block<D, CERT>((gfloat*)out_abs, np_out, (gfloat*)in_off, (gfloat*)in_hdr, (gfloat*)in_A,
+                       (gdouble*)in_Amax, ntiles_in, tps, part, (gctrl*)ctrl, eps_arg, blockIdx.x,
+                       blockIdx.y);
+}
+
+// Batched sweep: block i runs work item i = (problem, block of outputs, split)
+// of a list over several problems; the arithmetic per item is the same as in
+// the single-problem launch.
+template <int D, bool CERT>
+__global__ __launch_bounds__(kBlock) void k_sweep_batch(const BatchItem* __restrict__ items,
+                                                        const LaunchCtx* __restrict__ descs, int transpose) {
+  const BatchItem it = items[blockIdx.x];
+  const LaunchCtx& c = descs[it.prob];
+  const SideDev& out = transpose ? c.cols : c.rows;
+  const SideDev& in = transpose ? c.rows : c.cols;
+  const int splits = transpose ? c.splits_col : c.splits_row;
+  const int tps = (in.ntiles + splits - 1) / splits;
+  sweep_block<D, CERT>((gfloat*)out.abs, out.np, (gfloat*)in.off, (gfloat*)in.hdr, (gfloat*)in.A,
+                       (gdouble*)in.Amax, in.ntiles, tps, c.part.rec, (gctrl*)c.ctrl, -1.0, it.blk,
+                       it.split);
 }
 
 // ---------------------------------------------------------------------------
@@ -231,10 +268,13 @@ __device__ __forceinline__ void pack_weight(const SideDev& sd, int dim, int p, d
   }
 }
 
-__global__ __launch_bounds__(kTile) void k_finish(LaunchCtx c, int transpose, int kind, int splits,
-                                                  double eps_arg, double* __restrict__ lse_out) {
+// Merge + epilogue of one tile (bx) of 64 outputs; nblocks = tiles of the
+// output side (the column epilogue's last block advances k).
+__device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, int kind, int splits,
+                                             double eps_arg, double* __restrict__ lse_out, int bx,
+                                             int nblocks) {
   const SideDev& out = transpose ? c.cols : c.rows;
-  const int p = blockIdx.x * kTile + threadIdx.x;
+  const int p = bx * kTile + threadIdx.x;
   const int np = out.np;
   if (p >= np) return;
   const bool cert = (kind == kFinishColCert || kind == kFinishCertOnly);
@@ -300,11 +340,26 @@ __global__ __launch_bounds__(kTile) void k_finish(LaunchCtx c, int transpose, in
   // used it before counting itself here, and the next kernel sees the store
   if (threadIdx.x == 0) {
     const unsigned int done = atomicAdd(&c.ctrl->arrive, 1u);
-    if (done == gridDim.x - 1) {
+    if (done == (unsigned int)nblocks - 1) {
       c.ctrl->arrive = 0u;
       c.ctrl->k = k + 1;
     }
   }
+}
+
+__global__ __launch_bounds__(kTile) void k_finish(LaunchCtx c, int transpose, int kind, int splits,
+                                                  double eps_arg, double* __restrict__ lse_out) {
+  finish_block(c, transpose, kind, splits, eps_arg, lse_out, blockIdx.x, gridDim.x);
+}
+
+// Batched merge + epilogue: block i runs item i = (problem, output tile).
+__global__ __launch_bounds__(kTile) void k_finish_batch(const BatchItem* __restrict__ items,
+                                                        const LaunchCtx* __restrict__ descs, int transpose,
+                                                        int kind) {
+  const BatchItem it = items[blockIdx.x];
+  const LaunchCtx& c = descs[it.prob];
+  const SideDev& out = transpose ? c.cols : c.rows;
+  finish_block(c, transpose, kind, transpose ? c.splits_col : c.splits_row, -1.0, nullptr, it.blk, out.ntiles);
 }
 
 // lt and A_C of iteration k from the stored log beta^{k-1}, log beta^{k-2}.
@@ -379,15 +434,15 @@ __device__ void block_reduce_store(double* vals, int nv, double* dst) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cert_partial(LaunchCtx c) {
+__device__ __forceinline__ void cert_partial_block(const LaunchCtx& c, int bx, int nb) {
   double v[6] = {0, 0, 0, 0, 0, 0};
-  const int stride = gridDim.x * kBlock;
-  for (int p = blockIdx.x * kBlock + threadIdx.x; p < c.rows.count; p += stride) {
+  const int stride = nb * kBlock;
+  for (int p = bx * kBlock + threadIdx.x; p < c.rows.count; p += stride) {
     const double lah = c.st.lah[p];
     if (!isfinite(lah)) v[5] += 1.0;
     v[0] += c.rows.marg[p] * lah;
   }
-  for (int p = blockIdx.x * kBlock + threadIdx.x; p < c.cols.count; p += stride) {
+  for (int p = bx * kBlock + threadIdx.x; p < c.cols.count; p += stride) {
     const double lbh = c.st.lbh[p];
     const double cj = c.cols.marg[p];
     const double s = exp(c.st.logs[p]);
@@ -398,10 +453,18 @@ __global__ __launch_bounds__(kBlock) void k_cert_partial(LaunchCtx c) {
     v[3] += s * mu;
     v[4] += s;
   }
-  block_reduce_store(v, 6, c.cert_part + (size_t)blockIdx.x * 8);
+  block_reduce_store(v, 6, c.cert_part + (size_t)bx * 8);
 }
 
-__global__ __launch_bounds__(kBlock) void k_cert_final(LaunchCtx c) {
+__global__ __launch_bounds__(kBlock) void k_cert_partial(LaunchCtx c) { cert_partial_block(c, blockIdx.x, gridDim.x); }
+
+__global__ __launch_bounds__(kBlock) void k_cert_partial_batch(const BatchItem* __restrict__ items,
+                                                               const LaunchCtx* __restrict__ descs) {
+  const BatchItem it = items[blockIdx.x];
+  cert_partial_block(descs[it.prob], it.blk, descs[it.prob].cert_blocks);
+}
+
+__device__ __forceinline__ void cert_final_block(const LaunchCtx& c) {
   double v[6] = {0, 0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < c.cert_blocks; b += kBlock)
     for (int i = 0; i < 6; ++i) v[i] += c.cert_part[(size_t)b * 8 + i];
@@ -424,6 +487,21 @@ __global__ __launch_bounds__(kBlock) void k_cert_final(LaunchCtx c) {
     o[5] = costZ;
     o[6] = tot[4];
     o[7] = tot[5];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cert_final(LaunchCtx c) { cert_final_block(c); }
+
+// one block per listed problem; also copies the record into a contiguous array
+__global__ __launch_bounds__(kBlock) void k_cert_final_batch(const int* __restrict__ probs,
+                                                             const LaunchCtx* __restrict__ descs,
+                                                             double* __restrict__ records) {
+  const LaunchCtx& c = descs[probs[blockIdx.x]];
+  cert_final_block(c);
+  __syncthreads();
+  if (threadIdx.x < kCertSlots) {
+    __threadfence_block();
+    records[(size_t)blockIdx.x * kCertSlots + threadIdx.x] = c.cert_out[threadIdx.x];
   }
 }
 
@@ -506,6 +584,41 @@ __global__ void k_gather(const double* __restrict__ src, const int* __restrict__
 }
 
 }  // namespace
+
+hipError_t launch_sweep_batch(const BatchItem* items, int nitems, const LaunchCtx* descs, int dim,
+                              bool transpose, bool cert, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+#define BDRS_SWEEPB(DD, CC)                                                                       \
+  hipLaunchKernelGGL((k_sweep_batch<DD, CC>), dim3(nitems), dim3(kBlock), 0, s, items, descs,   \
+                     transpose ? 1 : 0)
+  switch (dim * 2 + (cert ? 1 : 0)) {
+    case 2: BDRS_SWEEPB(1, false); break;
+    case 3: BDRS_SWEEPB(1, true); break;
+    case 4: BDRS_SWEEPB(2, false); break;
+    case 5: BDRS_SWEEPB(2, true); break;
+    case 6: BDRS_SWEEPB(3, false); break;
+    case 7: BDRS_SWEEPB(3, true); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef BDRS_SWEEPB
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_batch(const BatchItem* items, int nitems, const LaunchCtx* descs, bool transpose,
+                               FinishKind kind, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finish_batch, dim3(nitems), dim3(kTile), 0, s, items, descs, transpose ? 1 : 0,
+                     (int)kind);
+  return hipGetLastError();
+}
+
+hipError_t launch_cert_batch(const BatchItem* items, int nitems, const int* probs, int nprobs,
+                             const LaunchCtx* descs, double* records, hipStream_t s) {
+  if (nitems <= 0 || nprobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cert_partial_batch, dim3(nitems), dim3(kBlock), 0, s, items, descs);
+  hipLaunchKernelGGL(k_cert_final_batch, dim3(nprobs), dim3(kBlock), 0, s, probs, descs, records);
+  return hipGetLastError();
+}
 
 int choose_splits(int np_out, int ntiles_in) {
   // enough (output wave, split) pairs to give every SIMD of the 256 CUs a few

@@ -1,0 +1,376 @@
+// Solve server: continuous batching of independent OT solves (bdrs_server_*).
+//
+// A worker thread owns the GPU work.  Requests wait in a FIFO queue; at every
+// block boundary the worker admits requests from the head of the queue while
+// a slot is free and the pool can hold the request's workspace, runs one
+// block of iterations of all running requests through the batch engine,
+// reads every request's certificate, and retires the finished ones (their
+// pool memory is reused by the next admissions).  The per-request arithmetic
+// is the single-problem one, so results do not depend on the mix.
+#include "bdrs_host.h"
+
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+using namespace bdrs_host;
+
+namespace {
+
+// First-fit allocator over [0, size) in 256-byte units (host bookkeeping only).
+class PoolAlloc {
+ public:
+  explicit PoolAlloc(size_t size) : size_(size) { free_[0] = size; }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = align_up(bytes ? bytes : 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        const size_t at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        used_ += bytes;
+        sizes_[*off] = bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off) {
+    auto s = sizes_.find(off);
+    if (s == sizes_.end()) return;
+    size_t bytes = s->second;
+    sizes_.erase(s);
+    used_ -= bytes;
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + bytes == next->first) {
+      bytes += next->second;
+      free_.erase(next);
+    }
+    auto it = free_.lower_bound(off);
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == off) {
+        prev->second += bytes;
+        return;
+      }
+    }
+    free_[off] = bytes;
+  }
+  size_t used() const { return used_; }
+  size_t size() const { return size_; }
+
+ private:
+  size_t size_, used_ = 0;
+  std::map<size_t, size_t> free_;    // offset -> bytes
+  std::map<size_t, size_t> sizes_;   // allocated offset -> bytes
+};
+
+struct Request {
+  uint64_t ticket = 0;
+  bdrs_params prm{};
+  std::vector<float> x, y;
+  std::vector<double> r, c;
+  double tau = 0;
+  int tau_relative = 1;
+  int max_iters = 0;
+  size_t bytes = 0, off = 0;
+  bdrs_solver solver = nullptr;
+  int iters = 0;
+  bdrs_result res{};
+};
+
+}  // namespace
+
+struct bdrs_server_ {
+  char* pool = nullptr;
+  int max_slots = 1, block_iters = 50, device = 0;
+  hipStream_t stream = nullptr;
+  std::chrono::steady_clock::time_point t0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  std::unique_ptr<PoolAlloc> alloc;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::vector<std::shared_ptr<Request>> running;
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> all;
+  std::thread worker;
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  void run();
+};
+
+namespace {
+
+void finish(bdrs_server_* sv, const std::shared_ptr<Request>& rq, int status) {
+  // called with the lock held
+  rq->res.state = 2;
+  rq->res.status = status;
+  rq->res.t_done = sv->now();
+  if (rq->solver) {
+    bdrs_destroy(rq->solver);
+    rq->solver = nullptr;
+  }
+  if (rq->bytes) {
+    sv->alloc->release(rq->off);
+    rq->bytes = 0;
+  }
+  rq->x.clear();
+  rq->y.clear();
+  rq->r.clear();
+  rq->c.clear();
+  rq->x.shrink_to_fit();
+  rq->y.shrink_to_fit();
+  rq->r.shrink_to_fit();
+  rq->c.shrink_to_fit();
+}
+
+}  // namespace
+
+void bdrs_server_::run() {
+  hipSetDevice(device);
+  BatchEngine eng;
+  size_t eng_off = 0, eng_bytes = 0;
+  bool eng_valid = false;
+  std::vector<double> rec;
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    // admission at the block boundary: FIFO while a slot and memory are free
+    bool changed = false;
+    while (!stop && !queue.empty() && (int)running.size() < max_slots) {
+      std::shared_ptr<Request> rq = queue.front();
+      size_t off = 0;
+      if (!alloc->alloc(rq->bytes, &off)) break;  // head of line waits for memory
+      queue.pop_front();
+      rq->off = off;
+      rq->prm.workspace = pool + off;
+      rq->prm.workspace_bytes = rq->bytes;
+      rq->prm.stream = stream;
+      lk.unlock();
+      bdrs_solver s = nullptr;
+      const bdrs_status st = create_from_host(&rq->prm, rq->x.data(), rq->y.data(), rq->r.data(), rq->c.data(), &s);
+      lk.lock();
+      if (st != BDRS_OK) {
+        finish(this, rq, st);
+        cv_done.notify_all();
+        continue;
+      }
+      rq->solver = s;
+      rq->res.state = 1;
+      rq->res.t_admit = now();
+      running.push_back(rq);
+      changed = true;
+    }
+    if (running.empty()) {
+      if (stop) break;
+      cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+      continue;
+    }
+    if (changed || !eng_valid) {
+      std::vector<bdrs_solver> mem;
+      for (auto& rq : running) mem.push_back(rq->solver);
+      const size_t need = BatchEngine::bytes_for(mem);
+      if (need > eng_bytes) {
+        if (eng_bytes) alloc->release(eng_off);
+        eng_bytes = 0;
+        if (!alloc->alloc(need, &eng_off)) {
+          // no room for the work lists: retire the newest request with NOMEM
+          auto rq = running.back();
+          running.pop_back();
+          finish(this, rq, BDRS_E_NOMEM);
+          cv_done.notify_all();
+          eng_valid = false;
+          continue;
+        }
+        eng_bytes = align_up(need);
+      }
+      lk.unlock();
+      const hipError_t e = eng.bind(mem, pool + eng_off, block_iters, false, stream);
+      lk.lock();
+      if (e != hipSuccess) {
+        for (auto& rq : running) finish(this, rq, BDRS_E_DEVICE);
+        running.clear();
+        cv_done.notify_all();
+        eng_valid = false;
+        continue;
+      }
+      eng_valid = true;
+    }
+    lk.unlock();
+    hipError_t e = eng.run_block();
+    if (e == hipSuccess) e = eng.read_records(rec);
+    lk.lock();
+    if (e != hipSuccess) {
+      for (auto& rq : running) finish(this, rq, BDRS_E_DEVICE);
+      running.clear();
+      eng_valid = false;
+      cv_done.notify_all();
+      continue;
+    }
+    std::vector<std::shared_ptr<Request>> still;
+    for (size_t q = 0; q < running.size(); ++q) {
+      auto& rq = running[q];
+      rq->solver->k += block_iters;
+      rq->iters += block_iters;
+      const bdrs_status cs = cert_from_record(rq->solver, rec.data() + q * kCertSlots, false, &rq->res.cert);
+      const bdrs_cert& ce = rq->res.cert;
+      const double target = rq->tau_relative ? ce.rel_gap_best : (ce.U_best - ce.L_best);
+      if (cs != BDRS_OK) finish(this, rq, cs);
+      else if (target <= rq->tau) finish(this, rq, BDRS_OK);
+      else if (rq->iters >= rq->max_iters) finish(this, rq, BDRS_NOT_CONVERGED);
+      else still.push_back(rq);
+    }
+    if (still.size() != running.size()) {
+      running.swap(still);
+      eng_valid = false;
+      cv_done.notify_all();
+    }
+    if (stop) {
+      for (auto& rq : running) finish(this, rq, BDRS_E_STATE);
+      running.clear();
+      break;
+    }
+  }
+  for (auto& rq : queue) finish(this, rq, BDRS_E_STATE);
+  queue.clear();
+  if (eng_bytes) alloc->release(eng_off);
+  cv_done.notify_all();
+}
+
+extern "C" {
+
+bdrs_status bdrs_server_create(void* pool, size_t pool_bytes, int32_t max_slots, int32_t block_iters,
+                               bdrs_server* out) {
+  if (!out) return fail(BDRS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!pool || ((uintptr_t)pool) % kAlign) return fail(BDRS_E_INVALID, "pool must be non-NULL and 256-byte aligned");
+  if (pool_bytes < kAlign) return fail(BDRS_E_INVALID, "pool_bytes too small");
+  if (max_slots < 1) return fail(BDRS_E_INVALID, "max_slots must be >= 1");
+  if (block_iters < 1) return fail(BDRS_E_INVALID, "block_iters must be >= 1");
+  bdrs_status st = check_device();
+  if (st != BDRS_OK) return st;
+  auto* sv = new bdrs_server_();
+  sv->pool = (char*)pool;
+  sv->max_slots = max_slots;
+  sv->block_iters = block_iters;
+  sv->alloc.reset(new PoolAlloc(pool_bytes / kAlign * kAlign));
+  sv->t0 = std::chrono::steady_clock::now();
+  hipError_t e = hipGetDevice(&sv->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete sv;
+    return fail(BDRS_E_DEVICE, "HIP error %s creating the server stream", hipGetErrorString(e));
+  }
+  sv->worker = std::thread([sv] { sv->run(); });
+  *out = sv;
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_server_submit(bdrs_server sv, const bdrs_request* rq, uint64_t* ticket) {
+  if (!sv) return fail(BDRS_E_INVALID, "server is NULL");
+  if (!rq || !ticket) return fail(BDRS_E_INVALID, "request and ticket are required");
+  bdrs_params p{};
+  p.m = rq->m;
+  p.n = rq->n;
+  p.dim = rq->dim;
+  p.x = rq->x;
+  p.y = rq->y;
+  p.r = rq->r;
+  p.c = rq->c;
+  p.cost_scale = rq->cost_scale;
+  p.eta = rq->eta;
+  p.lambda = rq->lambda;
+  p.omega = rq->omega;
+  p.workspace = sv->pool;  // placeholder for the checks; the real slot is assigned at admission
+  p.workspace_bytes = (size_t)-1;
+  bdrs_status st = check_params(&p);
+  if (st != BDRS_OK) return st;
+  if (!(rq->tau >= 0 && std::isfinite(rq->tau))) return fail(BDRS_E_INVALID, "tau must be finite and >= 0");
+  if (rq->max_iters < 1 || rq->max_iters % sv->block_iters)
+    return fail(BDRS_E_INVALID, "max_iters must be a positive multiple of block_iters (%d)", sv->block_iters);
+  auto r = std::make_shared<Request>();
+  r->prm = p;
+  r->bytes = make_layout(p.m, p.n, p.dim).total;
+  if (align_up(r->bytes) > sv->alloc->size())
+    return fail(BDRS_E_NOMEM, "request needs %zu bytes, the pool holds %zu", r->bytes, sv->alloc->size());
+  r->x.assign(rq->x, rq->x + (size_t)p.m * p.dim);
+  r->y.assign(rq->y, rq->y + (size_t)p.n * p.dim);
+  r->r.assign(rq->r, rq->r + p.m);
+  r->c.assign(rq->c, rq->c + p.n);
+  r->tau = rq->tau;
+  r->tau_relative = rq->tau_relative;
+  r->max_iters = rq->max_iters;
+  std::lock_guard<std::mutex> g(sv->mu);
+  if (sv->stop) return fail(BDRS_E_STATE, "server is stopping");
+  r->ticket = sv->next_ticket++;
+  r->res.state = 0;
+  r->res.t_submit = sv->now();
+  r->res.cert.repaired_cost = NAN;
+  sv->all[r->ticket] = r;
+  sv->queue.push_back(r);
+  *ticket = r->ticket;
+  sv->cv_work.notify_all();
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_server_poll(bdrs_server sv, uint64_t ticket, bdrs_result* out) {
+  if (!sv || !out) return fail(BDRS_E_INVALID, "server and out are required");
+  std::lock_guard<std::mutex> g(sv->mu);
+  auto it = sv->all.find(ticket);
+  if (it == sv->all.end()) return fail(BDRS_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  *out = it->second->res;
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_server_wait(bdrs_server sv, uint64_t ticket, bdrs_result* out) {
+  if (!sv || !out) return fail(BDRS_E_INVALID, "server and out are required");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->all.find(ticket);
+  if (it == sv->all.end()) return fail(BDRS_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  auto rq = it->second;
+  sv->cv_done.wait(lk, [&] { return rq->res.state == 2; });
+  *out = rq->res;
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_server_stats(bdrs_server sv, int32_t* running, int32_t* queued, size_t* pool_used) {
+  if (!sv) return fail(BDRS_E_INVALID, "server is NULL");
+  std::lock_guard<std::mutex> g(sv->mu);
+  if (running) *running = (int32_t)sv->running.size();
+  if (queued) *queued = (int32_t)sv->queue.size();
+  if (pool_used) *pool_used = sv->alloc->used();
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_server_now(bdrs_server sv, double* t) {
+  if (!sv || !t) return fail(BDRS_E_INVALID, "server and t are required");
+  *t = sv->now();
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_server_destroy(bdrs_server sv) {
+  if (!sv) return BDRS_OK;
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv_work.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  hipStreamSynchronize(sv->stream);
+  hipStreamDestroy(sv->stream);
+  delete sv;
+  return BDRS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+"""Solve server: a request's result in a mix of concurrent requests equals its
+result alone (bdrs_solve with cert_every = block_iters), bit for bit;
+admission respects the memory budget; invalid requests fail alone."""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2609_33814_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def alone(prob, eta, tau, cap, block):
+    from paper_2609_33814_amd import bdrs
+    d = torch.device("cuda:0")
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=d)
+    sv = bdrs.Solver(t(prob.x, torch.float32), t(prob.y, torch.float32), t(prob.r, torch.float64),
+                     t(prob.c, torch.float64), prob.cost_scale, eta=eta)
+    ok, ce = sv.solve(tau, cap, block)
+    sv.close()
+    return ok, ce
+
+
+def test_server_results_equal_alone_and_budget_is_respected():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_33814_amd import bdrs
+    sides = [16, 32, 24, 40, 16, 32, 48, 20]
+    probs = [inputs.grid_problem(s, 800 + 2 * i, 801 + 2 * i) for i, s in enumerate(sides)]
+    eta, tau, cap, block = 0.3, 0.02, 3000, 50
+    ref = [alone(p, eta, tau, cap, block) for p in probs]
+    # a pool that holds only a few requests at once forces queueing
+    need = max(bdrs.workspace_size(p.m, p.n, 2) for p in probs)
+    srv = bdrs.Server(pool_bytes=3 * need + (1 << 20), max_slots=4, block_iters=block)
+    tickets = []
+    peak = 0
+    for i, p in enumerate(probs):
+        tickets.append(srv.submit(p, eta=eta, tau=tau, max_iters=cap))
+        if i % 3 == 2:
+            time.sleep(0.01)                      # staggered arrivals
+        peak = max(peak, srv.stats()["running"])
+    res = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["running"] == 0 and st["queued"] == 0
+    assert peak <= 4
+    for (ok, ce), r in zip(ref, res):
+        assert r["state"] == 2
+        assert (r["status"] == bdrs.OK) == ok
+        for key in ("k", "L", "U", "L_best", "U_best", "rel_gap_best"):
+            assert r["cert"][key] == ce[key], key
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+
+
+def test_server_rejects_and_isolates_bad_requests():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_33814_amd import bdrs
+    srv = bdrs.Server(pool_bytes=64 << 20, max_slots=2, block_iters=50)
+    big = inputs.random_problem(1 << 20, 1 << 20, 2, 1)
+    assert bdrs.workspace_size(big.m, big.n, 2) > (64 << 20)
+    with pytest.raises(bdrs.BdrsError) as ei:          # can never fit the pool
+        srv.submit(big, max_iters=100)
+    assert ei.value.status == bdrs.E_NOMEM
+    good = inputs.grid_problem(16, 3, 4)
+    with pytest.raises(bdrs.BdrsError) as ei:          # max_iters not a block multiple
+        srv.submit(good, max_iters=75)
+    assert ei.value.status == bdrs.E_INVALID
+    bad = inputs.grid_problem(16, 5, 6)
+    bad.r = bad.r.copy()
+    bad.r[3] = -1.0                                     # contents are checked at admission
+    tb = srv.submit(bad, max_iters=100)
+    tg = srv.submit(good, eta=0.3, tau=0.05, max_iters=2000)
+    rb, rg = srv.wait(tb), srv.wait(tg)
+    srv.close()
+    assert rb["status"] == bdrs.E_INVALID
+    assert rg["status"] in (bdrs.OK, bdrs.NOT_CONVERGED) and rg["cert"]["k"] >= 49
