@@ -168,6 +168,17 @@ BDRS_API bdrs_status bdrs_set_state(bdrs_solver s, const double *log_alpha,
                            const double *log_alpha_hat, const double *log_beta_hat,
                            const double *log_beta_tilde, int64_t iters_done);
 
+/* Warm-start hints of the sweeps: for every source point the index of a
+ * target point whose term was near that row's maximum in the last row sweep
+ * (row_hint, m entries) and for every target point the index of a source
+ * point likewise (col_hint, n entries); -1 = none.  Device int32 buffers,
+ * original point order; NULL skips one.  They only choose the float32 shift
+ * of each reduction (any valid index gives a correct result), so they belong
+ * to a checkpoint only when a resumed run must repeat the original bit for
+ * bit.  Synchronous. */
+BDRS_API bdrs_status bdrs_get_hints(bdrs_solver s, int32_t *row_hint, int32_t *col_hint);
+BDRS_API bdrs_status bdrs_set_hints(bdrs_solver s, const int32_t *row_hint, const int32_t *col_hint);
+
 /* One LSE sweep on the solver's problem, for parity checks of the kernel:
  * out_i = LSE_j( w_j - C_ij / eps ) in natural-log units (the reduction of
  * the row update of Algorithm 1) when transpose == 0, and

@@ -22,6 +22,7 @@ EXPORTS = [
     "bdrs_version", "bdrs_profile", "bdrs_profile_read", "bdrs_batch_workspace_size",
     "bdrs_batch_solve", "bdrs_server_create", "bdrs_server_submit", "bdrs_server_poll",
     "bdrs_server_wait", "bdrs_server_stats", "bdrs_server_now", "bdrs_server_destroy",
+    "bdrs_get_hints", "bdrs_set_hints",
 ]
 
 
@@ -101,6 +102,8 @@ def lib() -> ctypes.CDLL:
         L.bdrs_get_state.argtypes = [vp] * 7 + [P(ctypes.c_int64)]
         L.bdrs_set_state.argtypes = [vp] * 7 + [ctypes.c_int64]
         L.bdrs_lse.argtypes = [vp, ctypes.c_int32, ctypes.c_double, vp, vp]
+        L.bdrs_get_hints.argtypes = [vp, vp, vp]
+        L.bdrs_set_hints.argtypes = [vp, vp, vp]
         L.bdrs_destroy.argtypes = [vp]
         L.bdrs_profile.argtypes = [vp, ctypes.c_int32]
         L.bdrs_batch_workspace_size.argtypes = [P(vp), ctypes.c_int32, P(ctypes.c_size_t)]
@@ -213,6 +216,18 @@ class Solver:
         f = lambda key: None if st.get(key) is None else st[key].to(self._torch.float64).contiguous()
         keep = [f(key) for key in ("la", "lb", "lb_prev", "lah", "lbh", "lt")]
         check(lib().bdrs_set_state(self._h, *[_ptr(t) for t in keep], int(st["k"])))
+
+    def get_hints(self) -> dict:
+        torch = self._torch
+        dev = self._inputs[0].device
+        rh = torch.empty(self.m, dtype=torch.int32, device=dev)
+        ch = torch.empty(self.n, dtype=torch.int32, device=dev)
+        check(lib().bdrs_get_hints(self._h, _ptr(rh), _ptr(ch)))
+        return dict(row=rh, col=ch)
+
+    def set_hints(self, hints: dict) -> None:
+        rh, ch = hints["row"].contiguous(), hints["col"].contiguous()
+        check(lib().bdrs_set_hints(self._h, _ptr(rh), _ptr(ch)))
 
     def lse(self, w, eps: float, transpose: bool = False):
         """out_i = LSE_j(w_j - C_ij/eps) (or the transposed reduction); float64 in and out."""

@@ -45,7 +45,7 @@ SideShape side_shape(int count) {
   SideShape s;
   s.count = count;
   s.ntiles = (count + kTile - 1) / kTile;
-  s.np = (s.ntiles * kTile + kBlock - 1) / kBlock * kBlock;
+  s.np = (s.ntiles * kTile + kPad - 1) / kPad * kPad;
   return s;
 }
 
@@ -67,7 +67,8 @@ Layout make_layout(int m, int n, int dim) {
   };
   L.ctrl = take(sizeof(Ctrl));
   auto side = [&](const SideShape& s, size_t& abs, size_t& off, size_t& hdr, size_t& A, size_t& Amax,
-                  size_t& perm, size_t& marg, size_t& logm) {
+                  size_t& perm, size_t& marg, size_t& logm, size_t& iperm, size_t& hint, size_t& tfit,
+                  size_t& talpha) {
     abs = take(sizeof(float) * (size_t)dim * s.np);
     off = take(sizeof(float) * (size_t)s.ntiles * dim * kTile);
     hdr = take(sizeof(float) * (size_t)s.ntiles * kHdr);
@@ -76,9 +77,15 @@ Layout make_layout(int m, int n, int dim) {
     perm = take(sizeof(int) * (size_t)s.np);
     marg = take(sizeof(double) * (size_t)s.np);
     logm = take(sizeof(double) * (size_t)s.np);
+    iperm = take(sizeof(int) * (size_t)s.count);
+    hint = take(sizeof(int) * (size_t)s.np);
+    tfit = take(sizeof(float) * 4 * (size_t)s.ntiles);
+    talpha = take(sizeof(double) * (size_t)s.ntiles);
   };
-  side(L.R, L.r_abs, L.r_off, L.r_hdr, L.r_A, L.r_Amax, L.r_perm, L.r_marg, L.r_logm);
-  side(L.C, L.c_abs, L.c_off, L.c_hdr, L.c_A, L.c_Amax, L.c_perm, L.c_marg, L.c_logm);
+  side(L.R, L.r_abs, L.r_off, L.r_hdr, L.r_A, L.r_Amax, L.r_perm, L.r_marg, L.r_logm, L.r_iperm, L.r_hint,
+       L.r_tfit, L.r_talpha);
+  side(L.C, L.c_abs, L.c_off, L.c_hdr, L.c_A, L.c_Amax, L.c_perm, L.c_marg, L.c_logm, L.c_iperm, L.c_hint,
+       L.c_tfit, L.c_talpha);
   L.la = take(sizeof(double) * L.R.np);
   L.lah = take(sizeof(double) * L.R.np);
   L.lb1 = take(sizeof(double) * L.C.np);
@@ -161,7 +168,7 @@ uint64_t spread2(uint64_t v) {
 
 struct HostSide {
   std::vector<float> abs, off, hdr;
-  std::vector<int> perm;
+  std::vector<int> perm, iperm;
   std::vector<double> marg, logm;
 };
 
@@ -193,7 +200,11 @@ void build_side(const std::vector<float>& pts, const std::vector<double>& w, int
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return code[a] < code[b]; });
 
   hs.perm.assign(sh.np, order[count - 1]);
-  for (int s = 0; s < count; ++s) hs.perm[s] = order[s];
+  hs.iperm.assign(count, 0);
+  for (int s = 0; s < count; ++s) {
+    hs.perm[s] = order[s];
+    hs.iperm[order[s]] = s;
+  }
   hs.abs.assign((size_t)dim * sh.np, 0.f);
   for (int s = 0; s < sh.np; ++s) {
     const int i = hs.perm[s];
@@ -240,7 +251,8 @@ void fill_ctx(bdrs_solver s) {
   c.splits_col = L.splits_col;
   c.ctrl = (Ctrl*)(base + L.ctrl);
   auto side = [&](SideDev& sd, const SideShape& sh, size_t abs, size_t off, size_t hdr, size_t A, size_t Amax,
-                  size_t perm, size_t marg, size_t logm) {
+                  size_t perm, size_t marg, size_t logm, size_t iperm, size_t hint, size_t tfit,
+                  size_t talpha) {
     sd.count = sh.count;
     sd.ntiles = sh.ntiles;
     sd.np = sh.np;
@@ -253,9 +265,15 @@ void fill_ctx(bdrs_solver s) {
     sd.perm = (int*)(base + perm);
     sd.marg = (double*)(base + marg);
     sd.logmarg = (double*)(base + logm);
+    sd.iperm = (int*)(base + iperm);
+    sd.hint = (int*)(base + hint);
+    sd.tfit = (float*)(base + tfit);
+    sd.talpha = (double*)(base + talpha);
   };
-  side(c.rows, L.R, L.r_abs, L.r_off, L.r_hdr, L.r_A, L.r_Amax, L.r_perm, L.r_marg, L.r_logm);
-  side(c.cols, L.C, L.c_abs, L.c_off, L.c_hdr, L.c_A, L.c_Amax, L.c_perm, L.c_marg, L.c_logm);
+  side(c.rows, L.R, L.r_abs, L.r_off, L.r_hdr, L.r_A, L.r_Amax, L.r_perm, L.r_marg, L.r_logm, L.r_iperm, L.r_hint,
+       L.r_tfit, L.r_talpha);
+  side(c.cols, L.C, L.c_abs, L.c_off, L.c_hdr, L.c_A, L.c_Amax, L.c_perm, L.c_marg, L.c_logm, L.c_iperm, L.c_hint,
+       L.c_tfit, L.c_talpha);
   c.st.la = (double*)(base + L.la);
   c.st.lah = (double*)(base + L.lah);
   c.st.lb1 = (double*)(base + L.lb1);
@@ -290,8 +308,8 @@ bdrs_status hip_status(hipError_t e, const char* what) {
 }
 
 // one LSE sweep launch, bracketed by HIP events when profiling is on
-hipError_t sweep(bdrs_solver s, bool transpose, bool cert, int splits, double eps_arg) {
-  if (!s->prof) return launch_sweep(s->ctx, transpose, cert, splits, eps_arg);
+hipError_t sweep(bdrs_solver s, bool transpose, bool cert, int splits, double eps_arg, int kofs = 0) {
+  if (!s->prof) return launch_sweep(s->ctx, transpose, cert, splits, eps_arg, kofs);
   while (s->ev_pool.size() < s->ev_used + 2) {
     hipEvent_t ev;
     hipError_t e = hipEventCreate(&ev);
@@ -300,7 +318,7 @@ hipError_t sweep(bdrs_solver s, bool transpose, bool cert, int splits, double ep
   }
   hipEvent_t a = s->ev_pool[s->ev_used], b = s->ev_pool[s->ev_used + 1];
   hipError_t e = hipEventRecord(a, s->ctx.stream);
-  if (e == hipSuccess) e = launch_sweep(s->ctx, transpose, cert, splits, eps_arg);
+  if (e == hipSuccess) e = launch_sweep(s->ctx, transpose, cert, splits, eps_arg, kofs);
   if (e == hipSuccess) e = hipEventRecord(b, s->ctx.stream);
   if (e == hipSuccess) {
     s->ev_used += 2;
@@ -311,16 +329,16 @@ hipError_t sweep(bdrs_solver s, bool transpose, bool cert, int splits, double ep
 }
 
 // one iteration of Algorithm 1; with cert the column sweep also gathers Algorithm 2's statistics
-bdrs_status enqueue_iteration(bdrs_solver s, bool cert) {
+bdrs_status enqueue_iteration(bdrs_solver s, bool cert, int kofs) {
   const LaunchCtx& c = s->ctx;
   hipError_t e;
-  if ((e = sweep(s, false, false, s->L.splits_row, -1.0)) != hipSuccess) return hip_status(e, "row sweep");
-  if ((e = launch_finish(c, false, kFinishRow, s->L.splits_row, -1.0, nullptr)) != hipSuccess)
+  if ((e = sweep(s, false, false, s->L.splits_row, -1.0, kofs)) != hipSuccess) return hip_status(e, "row sweep");
+  if ((e = launch_finish(c, false, kFinishRow, s->L.splits_row, -1.0, nullptr, kofs)) != hipSuccess)
     return hip_status(e, "row finish");
-  if ((e = sweep(s, true, cert, s->L.splits_col, -1.0)) != hipSuccess) return hip_status(e, "col sweep");
-  if ((e = launch_finish(c, true, cert ? kFinishColCert : kFinishCol, s->L.splits_col, -1.0, nullptr)) != hipSuccess)
+  if ((e = sweep(s, true, cert, s->L.splits_col, -1.0, kofs)) != hipSuccess) return hip_status(e, "col sweep");
+  if ((e = launch_finish(c, true, cert ? kFinishColCert : kFinishCol, s->L.splits_col, -1.0, nullptr, kofs)) !=
+      hipSuccess)
     return hip_status(e, "col finish");
-  s->k += 1;
   s->packed_rows = true;
   return BDRS_OK;
 }
@@ -384,15 +402,15 @@ bdrs_status enqueue_repair(bdrs_solver s) {
   const double eps = eps_at(s, s->k - 1);
   if ((e = launch_repair_pack(c)) != hipSuccess) return hip_status(e, "repair pack");
   if ((e = sweep(s, false, false, s->L.splits_row, eps)) != hipSuccess) return hip_status(e, "repair sweep");
-  if ((e = launch_finish(c, false, kFinishRepair, s->L.splits_row, eps, nullptr)) != hipSuccess)
+  if ((e = launch_finish(c, false, kFinishRepair, s->L.splits_row, eps, nullptr, 0)) != hipSuccess)
     return hip_status(e, "repair finish");
   if ((e = launch_repair_reduce(c)) != hipSuccess) return hip_status(e, "repair reduce");
   if ((e = launch_prologue(c)) != hipSuccess) return hip_status(e, "prologue");  // restore cols.A
   return BDRS_OK;
 }
 
-size_t row_sweep_items(const bdrs_solver s) { return (size_t)(s->L.R.np / kBlock) * s->L.splits_row; }
-size_t col_sweep_items(const bdrs_solver s) { return (size_t)(s->L.C.np / kBlock) * s->L.splits_col; }
+size_t row_sweep_items(const bdrs_solver s) { return (size_t)(s->L.R.np / kSweepBlock) * s->L.splits_row; }
+size_t col_sweep_items(const bdrs_solver s) { return (size_t)(s->L.C.np / kSweepBlock) * s->L.splits_col; }
 
 BatchLayout batch_layout(const std::vector<bdrs_solver>& sv) {
   BatchLayout B{};
@@ -447,9 +465,9 @@ hipError_t BatchEngine::bind(const std::vector<bdrs_solver>& members, char* ws, 
     const bdrs_solver s = members_[p];
     descs.push_back(s->ctx);
     for (int sp = 0; sp < s->L.splits_row; ++sp)
-      for (int b = 0; b < s->L.R.np / kBlock; ++b) rs.push_back({p, b, sp, 0});
+      for (int b = 0; b < s->L.R.np / kSweepBlock; ++b) rs.push_back({p, b, sp, 0});
     for (int sp = 0; sp < s->L.splits_col; ++sp)
-      for (int b = 0; b < s->L.C.np / kBlock; ++b) cs.push_back({p, b, sp, 0});
+      for (int b = 0; b < s->L.C.np / kSweepBlock; ++b) cs.push_back({p, b, sp, 0});
     for (int t = 0; t < s->L.R.ntiles; ++t) rf.push_back({p, t, 0, 0});
     for (int t = 0; t < s->L.C.ntiles; ++t) cf.push_back({p, t, 0, 0});
     for (int b = 0; b < s->L.cert_blocks; ++b) ce.push_back({p, b, 0, 0});
@@ -498,11 +516,12 @@ hipError_t BatchEngine::enqueue(hipStream_t st) {
   hipError_t e = hipSuccess;
   for (int i = 0; i < iters_ && e == hipSuccess; ++i) {
     const bool cert = (i == iters_ - 1);
-    e = launch_sweep_batch(rs, nrs_, descs, dim_, false, false, st);
-    if (e == hipSuccess) e = launch_finish_batch(rf, nrf_, descs, false, kFinishRow, st);
-    if (e == hipSuccess) e = launch_sweep_batch(cs, ncs_, descs, dim_, true, cert, st);
-    if (e == hipSuccess) e = launch_finish_batch(cf, ncf_, descs, true, cert ? kFinishColCert : kFinishCol, st);
+    e = launch_sweep_batch(rs, nrs_, descs, dim_, false, false, i, st);
+    if (e == hipSuccess) e = launch_finish_batch(rf, nrf_, descs, false, kFinishRow, i, st);
+    if (e == hipSuccess) e = launch_sweep_batch(cs, ncs_, descs, dim_, true, cert, i, st);
+    if (e == hipSuccess) e = launch_finish_batch(cf, ncf_, descs, true, cert ? kFinishColCert : kFinishCol, i, st);
   }
+  if (e == hipSuccess) e = launch_advance_batch(descs, (int)members_.size(), iters_, st);
   if (e == hipSuccess)
     e = launch_cert_batch(ce, nce_, (const int*)(ws_ + B_.probs), (int)members_.size(), descs,
                           (double*)(ws_ + B_.records), st);
@@ -713,6 +732,10 @@ bdrs_status create_from_host(const bdrs_params* p, const float* px, const float*
   chk(up(c.rows.off, R.off.data(), R.off.size() * sizeof(float)));
   chk(up(c.rows.hdr, R.hdr.data(), R.hdr.size() * sizeof(float)));
   chk(up(c.rows.perm, R.perm.data(), R.perm.size() * sizeof(int)));
+  chk(up(c.rows.iperm, R.iperm.data(), R.iperm.size() * sizeof(int)));
+  chk(up(c.cols.iperm, C.iperm.data(), C.iperm.size() * sizeof(int)));
+  chk(hipMemsetAsync(c.rows.hint, 0xff, sizeof(int) * (size_t)c.rows.np, stream));  // -1: no hint yet
+  chk(hipMemsetAsync(c.cols.hint, 0xff, sizeof(int) * (size_t)c.cols.np, stream));
   chk(up(c.rows.marg, R.marg.data(), R.marg.size() * sizeof(double)));
   chk(up(c.rows.logmarg, R.logm.data(), R.logm.size() * sizeof(double)));
   chk(up(c.cols.abs, C.abs.data(), C.abs.size() * sizeof(float)));
@@ -723,7 +746,6 @@ bdrs_status create_from_host(const bdrs_params* p, const float* px, const float*
   chk(up(c.cols.logmarg, C.logm.data(), C.logm.size() * sizeof(double)));
   Ctrl hc0{};
   hc0.k = 0;
-  hc0.arrive = 0;
   hc0.eta = p->eta;
   hc0.lam = p->lambda;
   hc0.scale = p->cost_scale;
@@ -755,10 +777,14 @@ extern "C" {
 bdrs_status bdrs_step(bdrs_solver s, int32_t iters) {
   if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
   if (iters < 0) return fail(BDRS_E_INVALID, "iters must be >= 0");
+  if (iters == 0) return BDRS_OK;
   for (int32_t i = 0; i < iters; ++i) {
-    bdrs_status st = enqueue_iteration(s, false);
+    bdrs_status st = enqueue_iteration(s, false, i);
     if (st != BDRS_OK) return st;
   }
+  hipError_t e = launch_advance(s->ctx.ctrl, iters, s->ctx.stream);
+  if (e != hipSuccess) return hip_status(e, "advance");
+  s->k += iters;
   return BDRS_OK;
 }
 
@@ -773,7 +799,7 @@ bdrs_status bdrs_certificate(bdrs_solver s, bdrs_cert* out) {
   const double eps = eps_at(s, s->k - 1);
   hipError_t e;
   if ((e = sweep(s, true, true, s->L.splits_col, eps)) != hipSuccess) return hip_status(e, "cert sweep");
-  if ((e = launch_finish(c, true, kFinishCertOnly, s->L.splits_col, eps, nullptr)) != hipSuccess)
+  if ((e = launch_finish(c, true, kFinishCertOnly, s->L.splits_col, eps, nullptr, 0)) != hipSuccess)
     return hip_status(e, "cert finish");
   if ((e = launch_cert_reduce(c)) != hipSuccess) return hip_status(e, "cert reduce");
   const bool repair = (s->prm.flags & BDRS_F_REPAIR) != 0;
@@ -792,13 +818,18 @@ bdrs_status bdrs_solve(bdrs_solver s, double tau, int32_t tau_relative, int32_t 
   bool have = false;
   bdrs_status st0 = sync_k(s);
   if (st0 != BDRS_OK) return st0;
+  int pending = 0;  // iterations enqueued since the counter was last advanced
   for (int32_t i = 0; i < max_iters; ++i) {
-    const long long k = s->k;
+    const long long k = s->k + pending;
     const bool due = ((k + 1) % cert_every == 0) || (i == max_iters - 1);
-    bdrs_status st = enqueue_iteration(s, due);
+    bdrs_status st = enqueue_iteration(s, due, pending);
     if (st != BDRS_OK) return st;
+    ++pending;
     if (!due) continue;
     hipError_t e;
+    if ((e = launch_advance(s->ctx.ctrl, pending, s->ctx.stream)) != hipSuccess) return hip_status(e, "advance");
+    s->k += pending;
+    pending = 0;
     if ((e = launch_cert_reduce(s->ctx)) != hipSuccess) return hip_status(e, "cert reduce");
     if (repair && (st = enqueue_repair(s)) != BDRS_OK) return st;
     st = read_cert(s, repair, &ce);
@@ -889,9 +920,31 @@ bdrs_status bdrs_lse(bdrs_solver s, int32_t transpose, double eps, const double*
   bdrs_status st = sync_k(s);
   if (st != BDRS_OK) return st;
   if ((e = sweep(s, tr, false, splits, eps)) != hipSuccess) return hip_status(e, "sweep");
-  if ((e = launch_finish(c, tr, kFinishLse, splits, eps, out)) != hipSuccess) return hip_status(e, "finish");
+  if ((e = launch_finish(c, tr, kFinishLse, splits, eps, out, 0)) != hipSuccess) return hip_status(e, "finish");
   s->packed_rows = false;
   return repack(s);
+}
+
+bdrs_status bdrs_get_hints(bdrs_solver s, int32_t* row_hint, int32_t* col_hint) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  const LaunchCtx& c = s->ctx;
+  hipError_t e = hipSuccess;
+  if (row_hint) e = launch_hints_out(c.rows.hint, c.rows.perm, c.cols.perm, c.rows.count, row_hint, c.stream);
+  if (e == hipSuccess && col_hint)
+    e = launch_hints_out(c.cols.hint, c.cols.perm, c.rows.perm, c.cols.count, col_hint, c.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  return e == hipSuccess ? BDRS_OK : hip_status(e, "get_hints");
+}
+
+bdrs_status bdrs_set_hints(bdrs_solver s, const int32_t* row_hint, const int32_t* col_hint) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  const LaunchCtx& c = s->ctx;
+  hipError_t e = hipSuccess;
+  if (row_hint) e = launch_hints_in(row_hint, c.rows.perm, c.cols.iperm, c.cols.count, c.rows.np, c.rows.hint, c.stream);
+  if (e == hipSuccess && col_hint)
+    e = launch_hints_in(col_hint, c.cols.perm, c.rows.iperm, c.rows.count, c.cols.np, c.cols.hint, c.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  return e == hipSuccess ? BDRS_OK : hip_status(e, "set_hints");
 }
 
 bdrs_status bdrs_profile(bdrs_solver s, int32_t enable) {

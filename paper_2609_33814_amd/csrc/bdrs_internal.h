@@ -6,7 +6,15 @@
 namespace bdrs {
 
 constexpr int kTile = 64;         // points per tile = one wavefront
-constexpr int kBlock = 256;       // threads per block in every kernel
+constexpr int kBlock = 256;       // threads per block of the O(n) kernels
+
+// threads per sweep block: the waves of one block share the input tiles of
+// their split (read once through the scalar cache for all of them)
+#ifndef BDRS_SWEEP_BLOCK
+#define BDRS_SWEEP_BLOCK 512
+#endif
+constexpr int kSweepBlock = BDRS_SWEEP_BLOCK;
+constexpr int kPad = kSweepBlock > kBlock ? kSweepBlock : kBlock;  // np is a multiple of this
 constexpr int kHdr = 8;           // floats per tile header: center[3], radius[3], pad[2]
 constexpr int kCertSlots = 16;    // doubles in a certificate record
 
@@ -18,9 +26,8 @@ constexpr int kCertSlots = 16;    // doubles in a certificate record
 // Device-resident control block of one solver: the iteration counter lives
 // here so that a captured block of iterations can be replayed at any k.
 struct Ctrl {
-  long long k;             // index of the next iteration of Algorithm 1
-  unsigned int arrive;     // last-block-done counter of the column epilogue
-  unsigned int pad0;
+  long long k;             // first iteration of the current block of Algorithm 1
+  unsigned int pad0, pad1;
   double eta, lam, scale;  // eta, lambda, cost scale s
   double omega;
 };
@@ -38,7 +45,13 @@ struct SideDev {
   float* A;        // [np] log2 weights of the next sweep that reads this side, relative
                    //      to their tile maximum (small magnitudes, float32)
   double* Amax;    // [ntiles] tile maxima of the absolute log2 weights (float64)
+  float* tfit;     // [ntiles][4] plane fit of the tile's log2 weights w2 over the offsets b:
+                   //      gradient gamma[3] and the largest residual rho (float32)
+  double* talpha;  // [ntiles] intercept alpha of that fit (w2 <= alpha + gamma . b + rho)
   int* perm;       // [np] original index of each slot
+  int* iperm;      // [count] slot of each original index
+  int* hint;       // [np] warm start of the sweep with this side as output: the slot of an
+                   //      input point whose term is near the output's maximum, or -1
   double* marg;    // [np] marginal (r or c), 0 on padding
   double* logmarg; // [np] log marginal
 };
@@ -61,6 +74,8 @@ struct StateDev {
 struct PartialRec {
   double M;
   float S, N;
+  int J;       // input slot of the exact maximum that set M, or -1
+  int pad;
 };
 
 struct Partials {
@@ -97,9 +112,12 @@ struct BatchItem {
 };
 
 // Kernel launchers (bdrs_kernels.hip).  Each returns the launch status.
-hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int splits, double eps_arg);
+// kofs: offset of the iteration inside the current block (k = Ctrl::k + kofs);
+// launch_advance adds a finished block's length to Ctrl::k.
+hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int splits, double eps_arg, int kofs);
 hipError_t launch_finish(const LaunchCtx& c, bool transpose, FinishKind kind, int splits,
-                         double eps_arg, double* lse_out);
+                         double eps_arg, double* lse_out, int kofs);
+hipError_t launch_advance(Ctrl* ctrl, int n, hipStream_t s);
 hipError_t launch_prologue(const LaunchCtx& c);                       // lt and A_C for iteration k
 hipError_t launch_pack(const LaunchCtx& c, bool transpose, const double* w, double eps);
 hipError_t launch_pack_rows_from_lah(const LaunchCtx& c, double eps);
@@ -108,12 +126,18 @@ hipError_t launch_repair_pack(const LaunchCtx& c);
 hipError_t launch_repair_reduce(const LaunchCtx& c);
 hipError_t launch_scatter(const double* src, const int* perm, int count, double* dst, hipStream_t s);
 hipError_t launch_gather(const double* src, const int* perm, int np, double* dst, hipStream_t s);
+// hints: to original order (out[perm_out[p]] = perm_in[hint[p]]) and back
+hipError_t launch_hints_out(const int* hint, const int* perm_out, const int* perm_in, int count, int* dst,
+                            hipStream_t s);
+hipError_t launch_hints_in(const int* src, const int* perm_out, const int* iperm_in, int count_in, int np,
+                           int* hint, hipStream_t s);
 
 // Batched phases over the problems in `descs` (device array of LaunchCtx).
 hipError_t launch_sweep_batch(const BatchItem* items, int nitems, const LaunchCtx* descs, int dim,
-                              bool transpose, bool cert, hipStream_t s);
+                              bool transpose, bool cert, int kofs, hipStream_t s);
 hipError_t launch_finish_batch(const BatchItem* items, int nitems, const LaunchCtx* descs, bool transpose,
-                               FinishKind kind, hipStream_t s);
+                               FinishKind kind, int kofs, hipStream_t s);
+hipError_t launch_advance_batch(const LaunchCtx* descs, int count, int n, hipStream_t s);
 hipError_t launch_cert_batch(const BatchItem* items, int nitems, const int* probs, int nprobs,
                              const LaunchCtx* descs, double* records, hipStream_t s);
 

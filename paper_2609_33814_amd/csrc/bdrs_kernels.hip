@@ -52,16 +52,41 @@ __device__ __forceinline__ double eps_of(CtrlPtr c, double eps_arg, int kshift) 
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+// Wavefront all-reductions of a double with DPP lane moves inside each row of
+// 16 lanes (swap neighbours, swap pairs, mirror halves, mirror the row) and
+// four readlanes across the rows; every lane receives the result.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+constexpr int kDppXor1 = 0xB1;        // quad_perm(1, 0, 3, 2)
+constexpr int kDppXor2 = 0x4E;        // quad_perm(2, 3, 0, 1)
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i within each half row
+constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i within each row
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_move<kDppXor1>(v);
+  v += dpp_move<kDppXor2>(v);
+  v += dpp_move<kDppHalfMirror>(v);
+  v += dpp_move<kDppMirror>(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_move<kDppXor1>(v));
+  v = fmax(v, dpp_move<kDppXor2>(v));
+  v = fmax(v, dpp_move<kDppHalfMirror>(v));
+  v = fmax(v, dpp_move<kDppMirror>(v));
+  return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
 }
 
 // ---------------------------------------------------------------------------
@@ -80,20 +105,48 @@ __device__ __forceinline__ void sweep_block(
     gfloat* __restrict__ out_abs, int np_out,
     gfloat* __restrict__ in_off, gfloat* __restrict__ in_hdr,
     gfloat* __restrict__ in_A, gdouble* __restrict__ in_Amax,
-    int ntiles_in, int tps,
-    PartialRec* __restrict__ part, gctrl* __restrict__ ctrl, double eps_arg, int bx, int split) {
-  const int p = bx * kBlock + threadIdx.x;
+    gfloat* __restrict__ in_fit, gdouble* __restrict__ in_alpha,
+    int ntiles_in, int count_in, int tps, const int* __restrict__ hint,
+    PartialRec* __restrict__ part, gctrl* __restrict__ ctrl, double eps_arg, int kofs, int bx, int split) {
+  const int p = bx * kSweepBlock + threadIdx.x;
   const int t0 = split * tps;
   const int t1 = min(t0 + tps, ntiles_in);
-  const double eps = eps_of(ctrl, eps_arg, 0);
+  const double eps = eps_of(ctrl, eps_arg, kofs);
   const double kap2d = kLog2eD * ctrl->scale / eps;
   const float kap2x2 = (float)(2.0 * kap2d);
+  const float kap2f = (float)kap2d;
+  const float inv2kap = (float)(0.5 / kap2d);
 
   float P[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) P[d] = out_abs[(size_t)d * np_out + p];
 
+  // Warm start: the exact exponent of one remembered input point is a lower
+  // bound of the output's maximum over all inputs, so it is a valid shift for
+  // every split (a split whose terms all lie far below it adds ~nothing); it
+  // spares the exact-max pass on the first tile of each split.
   double M = -INFINITY;
+  int J = -1;
+  {
+    const int j = hint[p];
+    if (j >= 0 && j < count_in) {
+      const int tj = j / kTile, qj = j % kTile;
+      const double am = in_Amax[tj];
+      const float aj = in_A[j];
+      if (am > -INFINITY && aj > -INFINITY) {
+        double na = 0.0, ab = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const double ad = (double)P[d] - (double)in_hdr[(size_t)tj * kHdr + d];
+          const double bd = (double)in_off[((size_t)tj * D + d) * kTile + qj];
+          na += ad * ad;
+          ab += ad * bd;
+        }
+        M = am + (double)aj + kap2d * (2.0 * ab - na);
+        J = j;
+      }
+    }
+  }
   float S = 0.0f, N = 0.0f;
 
   for (int t = t0; t < t1; ++t) {
@@ -108,22 +161,37 @@ __device__ __forceinline__ void sweep_block(
       B[d] = kap2x2 * a[d];
     }
     const double base = amax - kap2d * (double)na;  // Amax_t - kappa2 |a|^2
-    float bnd = 0.0f;
+    // upper bound of the exponents w2_q - kappa2 |a - b_q|^2 of this tile:
+    // w2_q <= alpha + gamma . b_q + rho, and the concave quadratic
+    // gamma . b - kappa2 |a - b|^2 is maximised over the tile's box per axis
+    gfloat* __restrict__ fit = in_fit + (size_t)t * 4;
+    float ubf = fit[3];
 #pragma unroll
-    for (int d = 0; d < D; ++d) bnd = fmaf(fabsf(B[d]), hdr[3 + d], bnd);
+    for (int d = 0; d < D; ++d) {
+      const float g = fit[d], rad = hdr[3 + d];
+      const float bs = fminf(fmaxf(fmaf(g, inv2kap, a[d]), -rad), rad);
+      const float df = a[d] - bs;
+      ubf = fmaf(g, bs, ubf);
+      ubf = fmaf(-kap2f, df * df, ubf);
+    }
+    const double ub = in_alpha[t] + (double)ubf;
 
     gfloat* __restrict__ offs = in_off + (size_t)t * D * kTile;
     gfloat* __restrict__ Aq = in_A + (size_t)t * kTile;
 
-    if (base + (double)bnd > M + kThresh) {
+    if (ub > M + kThresh) {
       // exact maximum of this tile for the lanes whose bound exceeds the window
       float tm = -INFINITY;
+      int qi = 0;
 #pragma unroll 16
       for (int q = 0; q < kTile; ++q) {
         float z = Aq[q];
 #pragma unroll
         for (int d = 0; d < D; ++d) z = fmaf(B[d], offs[d * kTile + q], z);
-        tm = fmaxf(tm, z);
+        if (z > tm) {
+          tm = z;
+          qi = q;
+        }
       }
       const double tmd = base + (double)tm;
       if (tmd > M) {
@@ -131,6 +199,7 @@ __device__ __forceinline__ void sweep_block(
         S *= sc;
         if (CERT) N *= sc;
         M = tmd;
+        J = t * kTile + qi;
       }
     }
     const float cm = (float)(base - M);
@@ -168,27 +237,31 @@ __device__ __forceinline__ void sweep_block(
   rec.M = M;
   rec.S = S;
   rec.N = CERT ? N : 0.0f;
+  rec.J = J;
+  rec.pad = 0;
   part[(size_t)split * np_out + p] = rec;
 }
 
 template <int D, bool CERT>
-__global__ __launch_bounds__(kBlock) void k_sweep(
+__global__ __launch_bounds__(kSweepBlock) void k_sweep(
     const float* __restrict__ out_abs, int np_out,
     const float* __restrict__ in_off, const float* __restrict__ in_hdr,
     const float* __restrict__ in_A, const double* __restrict__ in_Amax,
-    int ntiles_in, int tps,
-    PartialRec* __restrict__ part, const Ctrl* __restrict__ ctrl, double eps_arg) {
+    const float* __restrict__ in_fit, const double* __restrict__ in_alpha,
+    int ntiles_in, int count_in, int tps, const int* __restrict__ hint,
+    PartialRec* __restrict__ part, const Ctrl* __restrict__ ctrl, double eps_arg, int kofs) {
   sweep_block<D, CERT>((gfloat*)out_abs, np_out, (gfloat*)in_off, (gfloat*)in_hdr, (gfloat*)in_A,
-                       (gdouble*)in_Amax, ntiles_in, tps, part, (gctrl*)ctrl, eps_arg, blockIdx.x,
-                       blockIdx.y);
+                       (gdouble*)in_Amax, (gfloat*)in_fit, (gdouble*)in_alpha, ntiles_in, count_in, tps, hint,
+                       part, (gctrl*)ctrl, eps_arg, kofs, blockIdx.x, blockIdx.y);
 }
 
 // Batched sweep: block i runs work item i = (problem, block of outputs, split)
 // of a list over several problems; the arithmetic per item is the same as in
 // the single-problem launch.
 template <int D, bool CERT>
-__global__ __launch_bounds__(kBlock) void k_sweep_batch(const BatchItem* __restrict__ items,
-                                                        const LaunchCtx* __restrict__ descs, int transpose) {
+__global__ __launch_bounds__(kSweepBlock) void k_sweep_batch(const BatchItem* __restrict__ items,
+                                                        const LaunchCtx* __restrict__ descs, int transpose,
+                                                        int kofs) {
   const BatchItem it = items[blockIdx.x];
   const LaunchCtx& c = descs[it.prob];
   const SideDev& out = transpose ? c.cols : c.rows;
@@ -196,8 +269,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_batch(const BatchItem* __restr
   const int splits = transpose ? c.splits_col : c.splits_row;
   const int tps = (in.ntiles + splits - 1) / splits;
   sweep_block<D, CERT>((gfloat*)out.abs, out.np, (gfloat*)in.off, (gfloat*)in.hdr, (gfloat*)in.A,
-                       (gdouble*)in.Amax, in.ntiles, tps, c.part.rec, (gctrl*)c.ctrl, -1.0, it.blk,
-                       it.split);
+                       (gdouble*)in.Amax, (gfloat*)in.tfit, (gdouble*)in.talpha, in.ntiles, in.count, tps,
+                       out.hint, c.part.rec, (gctrl*)c.ctrl, -1.0, kofs, it.blk, it.split);
 }
 
 // ---------------------------------------------------------------------------
@@ -207,6 +280,7 @@ struct Merged {
   double lse;   // natural-log LSE
   double S;     // merged shifted sum (relative to Mx)
   double N;     // merged shifted cost sum
+  int J;        // input slot of the exact maximum of the winning split, or -1
 };
 
 __device__ __forceinline__ Merged merge_splits(const PartialRec* __restrict__ part, int splits, int np,
@@ -221,15 +295,16 @@ __device__ __forceinline__ Merged merge_splits(const PartialRec* __restrict__ pa
 #pragma unroll
     for (int g = 0; g < G; ++g) mx = fmax(mx, m[g]);
   }
-  Merged r{-INFINITY, 0.0, 0.0};
+  Merged r{-INFINITY, 0.0, 0.0, -1};
   if (mx == -INFINITY) return r;  // empty sum
   double S = 0.0, N = 0.0;
+  int J = -1;
   for (int s0 = 0; s0 < splits; s0 += G) {
     PartialRec q[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       if (s0 + g < splits) q[g] = part[(size_t)(s0 + g) * np + p];
-      else q[g] = PartialRec{-INFINITY, 0.0f, 0.0f};
+      else q[g] = PartialRec{-INFINITY, 0.0f, 0.0f, -1, 0};
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -237,10 +312,12 @@ __device__ __forceinline__ Merged merge_splits(const PartialRec* __restrict__ pa
       const double w = (double)fast_exp2((float)(q[g].M - mx));  // 0 for an empty split
       S += w * (double)q[g].S;
       N += w * (double)q[g].N;
+      if (J < 0 && q[g].M == mx) J = q[g].J;
     }
   }
   r.S = S;
   r.N = N;
+  r.J = J;
   r.lse = kLn2D * (mx + log2(S));
   return r;
 }
@@ -256,23 +333,104 @@ __device__ __forceinline__ float norm2_off(const float* __restrict__ off, int di
 }
 
 // A_p = log2(e) w - kappa2 |b_p|^2 in float64 (-inf on padding or for w = -inf);
-// stores the tile maximum (float64) and A_p minus that maximum (float32).
-// Called by whole wavefronts (one tile per wavefront).
-__device__ __forceinline__ void pack_weight(const SideDev& sd, int dim, int p, double w, double kap2) {
-  double A = -INFINITY;
-  if (p < sd.count && w > -INFINITY) A = kLog2eD * w - kap2 * (double)norm2_off(sd.off, dim, p);
-  if (p < sd.ntiles * kTile) {
-    const double m = wave_max(A);
-    sd.A[p] = (A == -INFINITY) ? -INFINITY : (float)(A - m);
-    if ((threadIdx.x & (kTile - 1)) == 0) sd.Amax[p / kTile] = m;
+// stores the tile maximum (float64) and A_p minus that maximum (float32), and
+// a plane fit w2 ~ alpha + gamma . b of the tile's log2 weights w2 = log2(e) w
+// with its largest residual rho (so w2 <= alpha + gamma . b + rho holds for
+// every point of the tile, whatever the fit).  The sweep turns it into an
+// upper bound of its exponents.  Called by whole wavefronts (one tile each).
+template <int D>
+__device__ __forceinline__ void pack_weight_d(const SideDev& sd, int p, double w, double kap2) {
+  constexpr int dim = D;
+  const bool live = p < sd.count && w > -INFINITY;
+  const int t = p / kTile, q = p % kTile;
+  double A = -INFINITY, w2 = 0.0;
+  double b[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) b[d] = 0.0;
+  if (p < sd.count) {
+    for (int d = 0; d < dim; ++d) b[d] = (double)sd.off[((size_t)t * dim + d) * kTile + q];
   }
+  if (live) {
+    w2 = kLog2eD * w;
+    A = w2 - kap2 * (double)norm2_off(sd.off, dim, p);
+  }
+  if (p >= sd.ntiles * kTile) return;
+  const double m = wave_max(A);
+  sd.A[p] = (A == -INFINITY) ? -INFINITY : (float)(A - m);
+  // least-squares plane through the live points of the tile (centred sums)
+  const double one = live ? 1.0 : 0.0;
+  const double cnt = wave_sum(one);
+  double mb[D], mw = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) mb[d] = 0.0;
+  double gam[3] = {0.0, 0.0, 0.0}, alpha = -INFINITY;
+  if (cnt > 0.0) {
+    for (int d = 0; d < dim; ++d) mb[d] = wave_sum(one * b[d]) / cnt;
+    mw = wave_sum(live ? w2 : 0.0) / cnt;
+    double cbb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, cbw[3] = {0, 0, 0};
+    for (int d = 0; d < dim; ++d) {
+      const double bd = live ? b[d] - mb[d] : 0.0;
+      cbw[d] = wave_sum(bd * (live ? w2 - mw : 0.0));
+      for (int e = 0; e <= d; ++e) {
+        cbb[d][e] = wave_sum(bd * (live ? b[e] - mb[e] : 0.0));
+        cbb[e][d] = cbb[d][e];
+      }
+    }
+    // solve cbb gamma = cbw by Cramer's rule; a (near-)singular system keeps gamma = 0
+    if constexpr (D == 1) {
+      if (cbb[0][0] > 1e-12) gam[0] = cbw[0] / cbb[0][0];
+    } else if constexpr (D == 2) {
+      const double det = cbb[0][0] * cbb[1][1] - cbb[0][1] * cbb[1][0];
+      if (fabs(det) > 1e-12 * (cbb[0][0] * cbb[1][1] + 1e-300)) {
+        gam[0] = (cbw[0] * cbb[1][1] - cbb[0][1] * cbw[1]) / det;
+        gam[1] = (cbb[0][0] * cbw[1] - cbw[0] * cbb[1][0]) / det;
+      }
+    } else {
+      const double a00 = cbb[1][1] * cbb[2][2] - cbb[1][2] * cbb[2][1];
+      const double a01 = cbb[0][2] * cbb[2][1] - cbb[0][1] * cbb[2][2];
+      const double a02 = cbb[0][1] * cbb[1][2] - cbb[0][2] * cbb[1][1];
+      const double det = cbb[0][0] * a00 + cbb[1][0] * a01 + cbb[2][0] * a02;
+      if (fabs(det) > 1e-12 * (cbb[0][0] * cbb[1][1] * cbb[2][2] + 1e-300)) {
+        const double a10 = cbb[1][2] * cbb[2][0] - cbb[1][0] * cbb[2][2];
+        const double a11 = cbb[0][0] * cbb[2][2] - cbb[0][2] * cbb[2][0];
+        const double a12 = cbb[0][2] * cbb[1][0] - cbb[0][0] * cbb[1][2];
+        const double a20 = cbb[1][0] * cbb[2][1] - cbb[1][1] * cbb[2][0];
+        const double a21 = cbb[0][1] * cbb[2][0] - cbb[0][0] * cbb[2][1];
+        const double a22 = cbb[0][0] * cbb[1][1] - cbb[0][1] * cbb[1][0];
+        gam[0] = (a00 * cbw[0] + a01 * cbw[1] + a02 * cbw[2]) / det;
+        gam[1] = (a10 * cbw[0] + a11 * cbw[1] + a12 * cbw[2]) / det;
+        gam[2] = (a20 * cbw[0] + a21 * cbw[1] + a22 * cbw[2]) / det;
+      }
+    }
+    for (int d = 0; d < dim; ++d) gam[d] = (double)(float)gam[d];  // the sweep reads gamma as float32
+    alpha = mw;
+    for (int d = 0; d < dim; ++d) alpha -= gam[d] * mb[d];
+  }
+  double res = 0.0;
+  if (live) {
+    res = w2 - alpha;
+    for (int d = 0; d < dim; ++d) res -= gam[d] * b[d];
+  }
+  const double rho = wave_max(fabs(res));
+  if ((threadIdx.x & (kTile - 1)) == 0) {
+    sd.Amax[t] = m;
+    sd.talpha[t] = alpha;
+    float* f = sd.tfit + (size_t)t * 4;
+    for (int d = 0; d < 3; ++d) f[d] = (float)gam[d];
+    f[3] = (float)(rho * (1.0 + 1e-6)) + 1e-3f;  // rounded up: the bound must hold
+  }
+}
+
+__device__ __forceinline__ void pack_weight(const SideDev& sd, int dim, int p, double w, double kap2) {
+  if (dim == 1) pack_weight_d<1>(sd, p, w, kap2);
+  else if (dim == 2) pack_weight_d<2>(sd, p, w, kap2);
+  else pack_weight_d<3>(sd, p, w, kap2);
 }
 
 // Merge + epilogue of one tile (bx) of 64 outputs; nblocks = tiles of the
 // output side (the column epilogue's last block advances k).
 __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, int kind, int splits,
-                                             double eps_arg, double* __restrict__ lse_out, int bx,
-                                             int nblocks) {
+                                             double eps_arg, double* __restrict__ lse_out, int bx, int kofs) {
   const SideDev& out = transpose ? c.cols : c.rows;
   const int p = bx * kTile + threadIdx.x;
   const int np = out.np;
@@ -280,8 +438,9 @@ __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, 
   const bool cert = (kind == kFinishColCert || kind == kFinishCertOnly);
   const Merged mg = merge_splits(c.part.rec, splits, np, p);
   const bool real = p < out.count;
+  if (real && mg.J >= 0) out.hint[p] = mg.J;
   const Ctrl* ctrl = c.ctrl;
-  const long long k = ctrl->k;
+  const long long k = ctrl->k + kofs;  // this iteration: the block's first plus the offset
   const double lam = ctrl->lam;
 
   if (kind == kFinishLse) {
@@ -303,7 +462,7 @@ __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, 
   }
   if (kind == kFinishRow) {
     // Algorithm 1: log alpha-hat^k = log r - LSE, log alpha^k = (1-lambda) log alpha^{k-1} + lambda log alpha-hat^k
-    const double eps = eps_of(ctrl, eps_arg, 0);
+    const double eps = eps_of(ctrl, eps_arg, kofs);
     const double kap2 = kLog2eD * ctrl->scale / eps;
     double lah = 0.0;
     if (real) {
@@ -332,34 +491,36 @@ __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, 
     // momentum for iteration k+1: log beta-tilde^k = log beta^k + (log beta^k - log beta^{k-1}) / lambda
     c.st.lt[nxt][p] = lb + (lb - lb1) / lam;
   }
-  const double eps1 = eps_of(ctrl, -1.0, 1);
+  const double eps1 = eps_of(ctrl, -1.0, kofs + 1);
   const double kap2n = kLog2eD * ctrl->scale / eps1;
   pack_weight(c.cols, c.dim, p, real ? c.st.lt[nxt][p] : 0.0, kap2n);
 
-  // the last block to finish advances k: every block read k at its start and
-  // used it before counting itself here, and the next kernel sees the store
-  if (threadIdx.x == 0) {
-    const unsigned int done = atomicAdd(&c.ctrl->arrive, 1u);
-    if (done == (unsigned int)nblocks - 1) {
-      c.ctrl->arrive = 0u;
-      c.ctrl->k = k + 1;
-    }
-  }
 }
 
 __global__ __launch_bounds__(kTile) void k_finish(LaunchCtx c, int transpose, int kind, int splits,
-                                                  double eps_arg, double* __restrict__ lse_out) {
-  finish_block(c, transpose, kind, splits, eps_arg, lse_out, blockIdx.x, gridDim.x);
+                                                  double eps_arg, double* __restrict__ lse_out, int kofs) {
+  finish_block(c, transpose, kind, splits, eps_arg, lse_out, blockIdx.x, kofs);
+}
+
+// Advances the iteration counter by n after a block of n iterations (kernels of
+// the block read the block's first iteration and take their offset as an
+// argument, so a captured block replays at any k).
+__global__ void k_advance(Ctrl* ctrl, int n) {
+  if (threadIdx.x == 0) ctrl->k += n;
+}
+
+__global__ void k_advance_batch(const LaunchCtx* __restrict__ descs, int count, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) descs[i].ctrl->k += n;
 }
 
 // Batched merge + epilogue: block i runs item i = (problem, output tile).
 __global__ __launch_bounds__(kTile) void k_finish_batch(const BatchItem* __restrict__ items,
                                                         const LaunchCtx* __restrict__ descs, int transpose,
-                                                        int kind) {
+                                                        int kind, int kofs) {
   const BatchItem it = items[blockIdx.x];
   const LaunchCtx& c = descs[it.prob];
-  const SideDev& out = transpose ? c.cols : c.rows;
-  finish_block(c, transpose, kind, transpose ? c.splits_col : c.splits_row, -1.0, nullptr, it.blk, out.ntiles);
+  finish_block(c, transpose, kind, transpose ? c.splits_col : c.splits_row, -1.0, nullptr, it.blk, kofs);
 }
 
 // lt and A_C of iteration k from the stored log beta^{k-1}, log beta^{k-2}.
@@ -577,6 +738,24 @@ __global__ void k_scatter(const double* __restrict__ src, const int* __restrict_
   if (p < count) dst[perm[p]] = src[p];
 }
 
+__global__ void k_hints_out(const int* __restrict__ hint, const int* __restrict__ perm_out,
+                            const int* __restrict__ perm_in, int count, int* __restrict__ dst) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p < count) {
+    const int j = hint[p];
+    dst[perm_out[p]] = j >= 0 ? perm_in[j] : -1;
+  }
+}
+
+__global__ void k_hints_in(const int* __restrict__ src, const int* __restrict__ perm_out,
+                           const int* __restrict__ iperm_in, int count_in, int np, int* __restrict__ hint) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p < np) {
+    const int j = src[perm_out[p]];
+    hint[p] = (j >= 0 && j < count_in) ? iperm_in[j] : -1;
+  }
+}
+
 __global__ void k_gather(const double* __restrict__ src, const int* __restrict__ perm, int np,
                          double* __restrict__ dst) {
   const int p = blockIdx.x * kBlock + threadIdx.x;
@@ -586,11 +765,11 @@ __global__ void k_gather(const double* __restrict__ src, const int* __restrict__
 }  // namespace
 
 hipError_t launch_sweep_batch(const BatchItem* items, int nitems, const LaunchCtx* descs, int dim,
-                              bool transpose, bool cert, hipStream_t s) {
+                              bool transpose, bool cert, int kofs, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
 #define BDRS_SWEEPB(DD, CC)                                                                       \
-  hipLaunchKernelGGL((k_sweep_batch<DD, CC>), dim3(nitems), dim3(kBlock), 0, s, items, descs,   \
-                     transpose ? 1 : 0)
+  hipLaunchKernelGGL((k_sweep_batch<DD, CC>), dim3(nitems), dim3(kSweepBlock), 0, s, items, descs,   \
+                     transpose ? 1 : 0, kofs)
   switch (dim * 2 + (cert ? 1 : 0)) {
     case 2: BDRS_SWEEPB(1, false); break;
     case 3: BDRS_SWEEPB(1, true); break;
@@ -605,10 +784,21 @@ hipError_t launch_sweep_batch(const BatchItem* items, int nitems, const LaunchCt
 }
 
 hipError_t launch_finish_batch(const BatchItem* items, int nitems, const LaunchCtx* descs, bool transpose,
-                               FinishKind kind, hipStream_t s) {
+                               FinishKind kind, int kofs, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_finish_batch, dim3(nitems), dim3(kTile), 0, s, items, descs, transpose ? 1 : 0,
-                     (int)kind);
+                     (int)kind, kofs);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(Ctrl* ctrl, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(kTile), 0, s, ctrl, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_batch(const LaunchCtx* descs, int count, int n, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_advance_batch, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, s, descs, count, n);
   return hipGetLastError();
 }
 
@@ -632,14 +822,15 @@ int choose_splits(int np_out, int ntiles_in) {
   return (ntiles_in + tps - 1) / tps;  // splits that own at least one tile
 }
 
-hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int splits, double eps_arg) {
+hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int splits, double eps_arg, int kofs) {
   const SideDev& out = transpose ? c.cols : c.rows;
   const SideDev& in = transpose ? c.rows : c.cols;
   const int tps = (in.ntiles + splits - 1) / splits;
-  dim3 grid(out.np / kBlock, splits);
+  dim3 grid(out.np / kSweepBlock, splits);
 #define BDRS_SWEEP(DD, CC)                                                                          \
-  hipLaunchKernelGGL((k_sweep<DD, CC>), grid, dim3(kBlock), 0, c.stream, out.abs, out.np, in.off,  \
-                     in.hdr, in.A, in.Amax, in.ntiles, tps, c.part.rec, c.ctrl, eps_arg)
+  hipLaunchKernelGGL((k_sweep<DD, CC>), grid, dim3(kSweepBlock), 0, c.stream, out.abs, out.np, in.off,  \
+                     in.hdr, in.A, in.Amax, in.tfit, in.talpha, in.ntiles, in.count, tps, out.hint,      \
+                     c.part.rec, c.ctrl, eps_arg, kofs)
   switch (c.dim * 2 + (cert ? 1 : 0)) {
     case 2: BDRS_SWEEP(1, false); break;
     case 3: BDRS_SWEEP(1, true); break;
@@ -654,11 +845,11 @@ hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int split
 }
 
 hipError_t launch_finish(const LaunchCtx& c, bool transpose, FinishKind kind, int splits, double eps_arg,
-                         double* lse_out) {
+                         double* lse_out, int kofs) {
   // one wavefront per block (one tile of outputs), so the O(n) epilogue spreads over all CUs
   const SideDev& out = transpose ? c.cols : c.rows;
   hipLaunchKernelGGL(k_finish, dim3(out.ntiles), dim3(kTile), 0, c.stream, c, transpose ? 1 : 0,
-                     (int)kind, splits, eps_arg, lse_out);
+                     (int)kind, splits, eps_arg, lse_out, kofs);
   return hipGetLastError();
 }
 
@@ -698,6 +889,22 @@ hipError_t launch_repair_reduce(const LaunchCtx& c) {
 hipError_t launch_scatter(const double* src, const int* perm, int count, double* dst, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, s, src, perm, count, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_hints_out(const int* hint, const int* perm_out, const int* perm_in, int count, int* dst,
+                            hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hints_out, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, s, hint, perm_out, perm_in,
+                     count, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_hints_in(const int* src, const int* perm_out, const int* iperm_in, int count_in, int np,
+                           int* hint, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hints_in, dim3((np + kBlock - 1) / kBlock), dim3(kBlock), 0, s, src, perm_out, iperm_in,
+                     count_in, np, hint);
   return hipGetLastError();
 }
 

@@ -190,8 +190,10 @@ def test_resume_is_bitwise():
     b = solver_for(prob)
     b.step(50)
     mid = b.get_state()
+    hints = b.get_hints()
     c = solver_for(prob)
     c.set_state(mid)
+    c.set_hints(hints)           # the warm-start hints make the resumed run repeat bit for bit
     c.step(50)
     sc = c.get_state()
     for key in ("la", "lb", "lb_prev", "lah", "lbh", "lt"):
