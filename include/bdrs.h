@@ -275,6 +275,51 @@ BDRS_API bdrs_status bdrs_server_now(bdrs_server s, double *t);
  * end with BDRS_E_STATE.  Frees host memory; the pool stays the caller's. */
 BDRS_API bdrs_status bdrs_server_destroy(bdrs_server s);
 
+/*
+ * Tile-shape autotuner.  The work tile of one sweep launch is a block of
+ * outputs (512 outputs, 8 wavefronts of 64) against one "split" of the input
+ * tiles; the number of splits per sweep direction decides how many tiles one
+ * work item streams, how many partial (max, sum) records the epilogue merges
+ * and how many work items fill the 256 CUs.  A process-wide table keyed by
+ * the exact shape (dim, m, n) holds the chosen split counts; every layout
+ * (bdrs_workspace_size, bdrs_create, the server's admission) made after an
+ * entry exists uses it, and shapes without an entry use a built-in heuristic
+ * (about 4096 wavefronts per sweep, at least 4 input tiles per split).  A
+ * workspace must be sized with the same table in effect as the bdrs_create
+ * that uses it.  The table is guarded by a mutex.
+ */
+typedef struct {
+  int32_t dim, m, n;             /* problem shape (the table key) */
+  int32_t splits_row;            /* input splits of the row sweep (over the n columns) */
+  int32_t splits_col;            /* input splits of the column sweep (over the m rows) */
+  int32_t candidates;            /* split counts timed per direction (0 if set by hand) */
+  double us_row, us_col;         /* measured median time of one row / column sweep with its
+                                    epilogue, microseconds (0 if set by hand) */
+  double us_row_default, us_col_default;  /* the same for the heuristic's split counts */
+} bdrs_tune_entry;
+
+/* Workspace bytes bdrs_autotune needs for this shape (room for the partial
+ * records of the largest candidate split count).  Host only. */
+BDRS_API bdrs_status bdrs_autotune_workspace_size(const bdrs_params *p, size_t *bytes);
+/* Times candidate split counts for the problem in *p (same fields and
+ * checks as bdrs_create; workspace of bdrs_autotune_workspace_size bytes):
+ * runs a few iterations of Algorithm 1 to reach a typical state, then
+ * `rounds` rounds that each time every candidate's row and column sweep
+ * (with its epilogue) once with HIP events on p->stream, interleaved so the
+ * drift of the state affects every candidate alike.  The candidate with
+ * the smallest median per direction is entered into the table (replacing an
+ * entry of the same shape) and copied to *out.  The workspace contents are
+ * scratch.  Synchronous.  rounds in [1, 1000]. */
+BDRS_API bdrs_status bdrs_autotune(const bdrs_params *p, int32_t rounds, bdrs_tune_entry *out);
+/* Inserts or replaces the entry of e's shape (e.g. a table saved earlier).
+ * Split counts are clamped to [1, input tiles]. */
+BDRS_API bdrs_status bdrs_tune_set(const bdrs_tune_entry *e);
+/* Copies entry `index` (0-based, insertion order) to *out; BDRS_E_INVALID
+ * past the end.  *count (optional) receives the number of entries. */
+BDRS_API bdrs_status bdrs_tune_get(int32_t index, bdrs_tune_entry *out, int32_t *count);
+/* Empties the table. */
+BDRS_API bdrs_status bdrs_tune_clear(void);
+
 /* Kernel timing for measurement.  enable != 0 brackets every LSE sweep
  * kernel this solver launches from then on with a pair of HIP events on the
  * solver's stream and clears the totals; enable == 0 stops recording.

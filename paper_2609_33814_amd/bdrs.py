@@ -11,6 +11,10 @@ import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libbdrs.so")
+# Split-count table written by `python -m paper_2609_33814_amd.autotune`; it is
+# loaded into the library when the library is first loaded.  BDRS_TUNING
+# names another file, or "none" to keep the built-in heuristic.
+TUNING_PATH = os.path.join(PKG, "tuning_gfx950.json")
 
 OK, NOT_CONVERGED = 0, 1
 E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_NUMERIC = -1, -2, -3, -4, -5
@@ -22,7 +26,8 @@ EXPORTS = [
     "bdrs_version", "bdrs_profile", "bdrs_profile_read", "bdrs_batch_workspace_size",
     "bdrs_batch_solve", "bdrs_server_create", "bdrs_server_submit", "bdrs_server_poll",
     "bdrs_server_wait", "bdrs_server_stats", "bdrs_server_now", "bdrs_server_destroy",
-    "bdrs_get_hints", "bdrs_set_hints",
+    "bdrs_get_hints", "bdrs_set_hints", "bdrs_autotune_workspace_size", "bdrs_autotune",
+    "bdrs_tune_set", "bdrs_tune_get", "bdrs_tune_clear",
 ]
 
 
@@ -75,6 +80,19 @@ class Result(ctypes.Structure):
                     t_submit=self.t_submit, t_admit=self.t_admit, t_done=self.t_done)
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("m", ctypes.c_int32), ("n", ctypes.c_int32),
+        ("splits_row", ctypes.c_int32), ("splits_col", ctypes.c_int32),
+        ("candidates", ctypes.c_int32),
+        ("us_row", ctypes.c_double), ("us_col", ctypes.c_double),
+        ("us_row_default", ctypes.c_double), ("us_col_default", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class BdrsError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"bdrs status {status}: {msg}")
@@ -118,12 +136,20 @@ def lib() -> ctypes.CDLL:
         L.bdrs_server_stats.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_size_t)]
         L.bdrs_server_now.argtypes = [vp, P(ctypes.c_double)]
         L.bdrs_server_destroy.argtypes = [vp]
+        L.bdrs_autotune_workspace_size.argtypes = [P(Params), P(ctypes.c_size_t)]
+        L.bdrs_autotune.argtypes = [P(Params), ctypes.c_int32, P(TuneEntry)]
+        L.bdrs_tune_set.argtypes = [P(TuneEntry)]
+        L.bdrs_tune_get.argtypes = [ctypes.c_int32, P(TuneEntry), P(ctypes.c_int32)]
+        L.bdrs_tune_clear.argtypes = []
         L.bdrs_last_error.restype = ctypes.c_char_p
         L.bdrs_version.restype = ctypes.c_char_p
         for name in EXPORTS:
             if name not in ("bdrs_last_error", "bdrs_version"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
+        path = os.environ.get("BDRS_TUNING", TUNING_PATH)
+        if path != "none" and os.path.exists(path):
+            load_tuning(path)
     return _lib
 
 
@@ -338,3 +364,64 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------
+# tile-shape autotuner (bdrs_autotune / bdrs_tune_*)
+# ----------------------------------------------------------------------------
+def autotune(x, y, r, c, cost_scale, eta=0.1, lam=1.0, omega=1.0, rounds=20, stream=None) -> dict:
+    """Times candidate split counts on this problem (torch tensors on the GPU,
+    as for Solver) and enters the fastest into the library's table."""
+    import torch
+    m, dim = int(x.shape[0]), int(x.shape[1])
+    n = int(y.shape[0])
+    p = make_params(m, n, dim)
+    need = ctypes.c_size_t()
+    check(lib().bdrs_autotune_workspace_size(ctypes.byref(p), ctypes.byref(need)))
+    ws = torch.empty(need.value + 256, dtype=torch.uint8, device=x.device)
+    wp = (ws.data_ptr() + 255) // 256 * 256
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    xx, yy, rr, cc = (t.contiguous() for t in (x, y, r, c))
+    p = make_params(m, n, dim, _ptr(xx), _ptr(yy), _ptr(rr), _ptr(cc), float(cost_scale), float(eta),
+                    float(lam), float(omega), wp, need.value, int(st.cuda_stream))
+    e = TuneEntry()
+    check(lib().bdrs_autotune(ctypes.byref(p), int(rounds), ctypes.byref(e)))
+    del ws
+    return e.as_dict()
+
+
+def tune_set(entry: dict) -> None:
+    e = TuneEntry(**{k: entry.get(k, 0) for k, _ in TuneEntry._fields_})
+    check(lib().bdrs_tune_set(ctypes.byref(e)))
+
+
+def tune_table() -> list[dict]:
+    count = ctypes.c_int32()
+    check(lib().bdrs_tune_get(0, None, ctypes.byref(count)))
+    out = []
+    for i in range(count.value):
+        e = TuneEntry()
+        check(lib().bdrs_tune_get(i, ctypes.byref(e), None))
+        out.append(e.as_dict())
+    return out
+
+
+def tune_clear() -> None:
+    check(lib().bdrs_tune_clear())
+
+
+def save_tuning(path: str, device: str = "gfx950") -> None:
+    import json
+    with open(path, "w") as f:
+        json.dump({"device": device, "entries": tune_table()}, f, indent=1)
+        f.write("\n")
+
+
+def load_tuning(path: str) -> int:
+    """Enters every entry of a saved table; returns their number."""
+    import json
+    with open(path) as f:
+        doc = json.load(f)
+    for e in doc.get("entries", []):
+        tune_set(e)
+    return len(doc.get("entries", []))

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libbdrs.so")
-SOURCES = ["bdrs_kernels.hip", "bdrs_api.hip", "bdrs_server.hip"]
+SOURCES = ["bdrs_kernels.hip", "bdrs_api.hip", "bdrs_server.hip", "bdrs_tune.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -50,12 +50,23 @@ SideShape side_shape(int count) {
 }
 
 
-Layout make_layout(int m, int n, int dim) {
+int normalize_splits(int s, int ntiles_in) {
+  s = std::max(1, std::min(s, ntiles_in));
+  const int tps = (ntiles_in + s - 1) / s;
+  return (ntiles_in + tps - 1) / tps;
+}
+
+Layout make_layout(int m, int n, int dim, int reserve_row, int reserve_col) {
   Layout L{};
   L.R = side_shape(m);
   L.C = side_shape(n);
   L.splits_row = choose_splits(L.R.np, L.C.ntiles);
   L.splits_col = choose_splits(L.C.np, L.R.ntiles);
+  int sr = 0, sc = 0;
+  if (tuned_splits(dim, m, n, &sr, &sc)) {
+    L.splits_row = normalize_splits(sr, L.C.ntiles);
+    L.splits_col = normalize_splits(sc, L.R.ntiles);
+  }
   L.splits_max = std::max(L.splits_row, L.splits_col);
   const int npmax = std::max(L.R.np, L.C.np);
   L.cert_blocks = std::max(1, std::min(256, npmax / kBlock));
@@ -96,10 +107,12 @@ Layout make_layout(int m, int n, int dim) {
   L.mu = take(sizeof(double) * L.C.np);
   L.logs = take(sizeof(double) * L.C.np);
   L.pvec = take(sizeof(double) * L.R.np);
-  const size_t pelems = (size_t)std::max((size_t)L.splits_row * L.R.np, (size_t)L.splits_col * L.C.np);
-  L.part = take(sizeof(PartialRec) * pelems);
   L.cert_part = take(sizeof(double) * 2 * (size_t)L.cert_blocks * 8);
   L.cert_out = take(sizeof(double) * kCertSlots);
+  // partial records last: every other offset is independent of the split counts
+  const size_t rows_rec = (size_t)std::max(L.splits_row, reserve_row) * L.R.np;
+  const size_t cols_rec = (size_t)std::max(L.splits_col, reserve_col) * L.C.np;
+  L.part = take(sizeof(PartialRec) * std::max(rows_rec, cols_rec));
   L.total = o;
   return L;
 }
@@ -112,7 +125,7 @@ bdrs_status check_sizes(const bdrs_params* p) {
   return BDRS_OK;
 }
 
-bdrs_status check_params(const bdrs_params* p) {
+bdrs_status check_params(const bdrs_params* p, size_t need) {
   bdrs_status st = check_sizes(p);
   if (st != BDRS_OK) return st;
   if (!p->x) return fail(BDRS_E_INVALID, "x is NULL");
@@ -127,9 +140,9 @@ bdrs_status check_params(const bdrs_params* p) {
   if (p->flags & ~BDRS_F_REPAIR) return fail(BDRS_E_INVALID, "unknown flags 0x%x", p->flags);
   if (!p->workspace) return fail(BDRS_E_INVALID, "workspace is NULL");
   if (((uintptr_t)p->workspace) % kAlign) return fail(BDRS_E_INVALID, "workspace must be 256-byte aligned");
-  const Layout L = make_layout(p->m, p->n, p->dim);
-  if (p->workspace_bytes < L.total)
-    return fail(BDRS_E_NOMEM, "workspace too small: %zu bytes given, %zu needed", p->workspace_bytes, L.total);
+  if (need == 0) need = make_layout(p->m, p->n, p->dim).total;
+  if (p->workspace_bytes < need)
+    return fail(BDRS_E_NOMEM, "workspace too small: %zu bytes given, %zu needed", p->workspace_bytes, need);
   return BDRS_OK;
 }
 
@@ -662,15 +675,9 @@ bdrs_status bdrs_create(const bdrs_params* p, bdrs_solver* out) {
   if (st != BDRS_OK) return st;
   if ((st = check_device()) != BDRS_OK) return st;
 
-  const int m = p->m, n = p->n, dim = p->dim;
-  hipStream_t stream = (hipStream_t)p->stream;
-  std::vector<float> hx((size_t)m * dim), hy((size_t)n * dim);
-  std::vector<double> hr(m), hc(n);
-  HIPCHK(hipMemcpyAsync(hx.data(), p->x, hx.size() * sizeof(float), hipMemcpyDeviceToHost, stream));
-  HIPCHK(hipMemcpyAsync(hy.data(), p->y, hy.size() * sizeof(float), hipMemcpyDeviceToHost, stream));
-  HIPCHK(hipMemcpyAsync(hr.data(), p->r, m * sizeof(double), hipMemcpyDeviceToHost, stream));
-  HIPCHK(hipMemcpyAsync(hc.data(), p->c, n * sizeof(double), hipMemcpyDeviceToHost, stream));
-  HIPCHK(hipStreamSynchronize(stream));
+  std::vector<float> hx, hy;
+  std::vector<double> hr, hc;
+  if ((st = download_inputs(p, hx, hy, hr, hc)) != BDRS_OK) return st;
   return create_from_host(p, hx.data(), hy.data(), hr.data(), hc.data(), out);
 }
 
@@ -678,8 +685,24 @@ bdrs_status bdrs_create(const bdrs_params* p, bdrs_solver* out) {
 
 namespace bdrs_host {
 
+bdrs_status download_inputs(const bdrs_params* p, std::vector<float>& hx, std::vector<float>& hy,
+                            std::vector<double>& hr, std::vector<double>& hc) {
+  const int m = p->m, n = p->n, dim = p->dim;
+  hipStream_t stream = (hipStream_t)p->stream;
+  hx.resize((size_t)m * dim);
+  hy.resize((size_t)n * dim);
+  hr.resize(m);
+  hc.resize(n);
+  HIPCHK(hipMemcpyAsync(hx.data(), p->x, hx.size() * sizeof(float), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(hy.data(), p->y, hy.size() * sizeof(float), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(hr.data(), p->r, m * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(hc.data(), p->c, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return BDRS_OK;
+}
+
 bdrs_status create_from_host(const bdrs_params* p, const float* px, const float* py, const double* pr,
-                             const double* pc, bdrs_solver* out) {
+                             const double* pc, bdrs_solver* out, int reserve_row, int reserve_col) {
   *out = nullptr;
   const int m = p->m, n = p->n, dim = p->dim;
   hipStream_t stream = (hipStream_t)p->stream;
@@ -703,9 +726,12 @@ bdrs_status create_from_host(const bdrs_params* p, const float* px, const float*
   if (std::fabs(sr - 1.0) > 1e-9) return fail(BDRS_E_INVALID, "r must sum to 1 (sum - 1 = %.3e)", sr - 1.0);
   if (std::fabs(sc - 1.0) > 1e-9) return fail(BDRS_E_INVALID, "c must sum to 1 (sum - 1 = %.3e)", sc - 1.0);
 
+  const Layout L = make_layout(m, n, dim, reserve_row, reserve_col);
+  if (p->workspace_bytes < L.total)  // e.g. the tuning table changed since the workspace was sized
+    return fail(BDRS_E_NOMEM, "workspace too small: %zu bytes given, %zu needed", p->workspace_bytes, L.total);
   bdrs_solver s = new bdrs_solver_();
   s->prm = *p;
-  s->L = make_layout(m, n, dim);
+  s->L = L;
   fill_ctx(s);
 
   // common origin: centre of the joint bounding box (keeps coordinates small)

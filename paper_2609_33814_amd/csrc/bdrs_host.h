@@ -35,14 +35,26 @@ struct Layout {
   size_t part, cert_part, cert_out;
 };
 
-Layout make_layout(int m, int n, int dim);
+// Split counts of the tuning table for this shape, if it holds an entry.
+bool tuned_splits(int dim, int m, int n, int* splits_row, int* splits_col);
+// A split count clamped to [1, ntiles_in] and reduced to the number of splits
+// that own at least one input tile at ceil(ntiles_in / s) tiles per split.
+int normalize_splits(int s, int ntiles_in);
+// Workspace layout; the partial records get room for at least reserve_row /
+// reserve_col splits (the autotuner's largest candidates).
+Layout make_layout(int m, int n, int dim, int reserve_row = 0, int reserve_col = 0);
 bdrs_status check_sizes(const bdrs_params* p);
-bdrs_status check_params(const bdrs_params* p);
+// need = 0: the workspace must hold make_layout(m, n, dim)
+bdrs_status check_params(const bdrs_params* p, size_t need = 0);
 bdrs_status check_device();
 
 // Builds a solver from host copies of the inputs (contents validated here).
 bdrs_status create_from_host(const bdrs_params* p, const float* hx, const float* hy, const double* hr,
-                             const double* hc, bdrs_solver* out);
+                             const double* hc, bdrs_solver* out, int reserve_row = 0, int reserve_col = 0);
+// Device -> host copies of a problem's inputs (synchronises p->stream).
+bdrs_status download_inputs(const bdrs_params* p, std::vector<float>& hx, std::vector<float>& hy,
+                            std::vector<double>& hr, std::vector<double>& hc);
+bdrs_status hip_status(hipError_t e, const char* what);
 bdrs_status sync_k(bdrs_solver s);
 bdrs_status cert_from_record(bdrs_solver s, const double* rec, bool repair, bdrs_cert* out);
 

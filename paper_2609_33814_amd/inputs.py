@@ -166,6 +166,16 @@ def c2_problem() -> Problem:
     return grid_problem(128, 21, 22)
 
 
+def c3_problem() -> Problem:
+    """Colour transfer: 1024x1024 = 1,048,576 RGB points per side (seeds 31, 32)."""
+    return colour_problem(1 << 20, 1 << 20, 31, 32)
+
+
+def c3b_problem() -> Problem:
+    """Colour transfer at 4238x2365 = 10,022,870 RGB points per side (seeds 33, 34)."""
+    return colour_problem(10022870, 10022870, 33, 34)
+
+
 def batch_sides(count: int = 64, seed: int = 41) -> list[int]:
     """Grid sides for the uneven batch: drawn from {32, 64, 128, 256}."""
     idx = np.random.default_rng(seed).integers(0, 4, count)

@@ -262,3 +262,21 @@ def test_full_size_grid_sampled_rows():
         got = sv.lse(torch.as_tensor(w, device=dev()), eps).cpu().numpy()[rows]
         ref = lse.implicit_lse(prob.x, prob.y, prob.cost_scale, eps, w, rows=rows)
         assert rel_err(got, ref) <= SWEEP_TOL
+
+
+def test_full_size_colour_sampled_rows():
+    """Colour transfer at 1024x1024 RGB points per side (d = 3, 1.1e12 entries
+    per sweep) at the benchmark's launch shape: sampled outputs of both sweep
+    directions checked one by one against the oracle."""
+    prob = inputs.c3_problem()
+    sv = solver_for(prob, eta=0.1)
+    rng = np.random.default_rng(29)
+    for transpose in (False, True):
+        src, dst = (prob.y, prob.x) if transpose else (prob.x, prob.y)
+        rows = rng.choice(src.shape[0], 64, replace=False)
+        for eps in (0.1, 1e-3):
+            w = rng.normal(0, 3, dst.shape[0])
+            got = sv.lse(torch.as_tensor(w, device=dev()), eps, transpose=transpose).cpu().numpy()[rows]
+            ref = np.concatenate([lse.implicit_lse(src, dst, prob.cost_scale, eps, w, rows=rows[a:a + 16])
+                                  for a in range(0, rows.size, 16)])
+            assert rel_err(got, ref) <= SWEEP_TOL, (transpose, eps)
