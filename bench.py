@@ -26,15 +26,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Gentries/s of fused LSE sweeps + time-to-1% rel. gap; p50/p99 serve latency"
-ETA = 0.1            # initial temperature of the grid workloads (tuning: see the design doc)
+ETA = 0.1            # initial temperature of the grid workloads (chosen from the oracle's gap curves)
 CERT_EVERY = 50
 CU, LANES, CLK = 256, 64, 2.4e9
-EXP_SLOTS = 2        # v_exp_f32 issues at half the FMA rate on gfx950
+EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters show 6.78 VALU
+                     # instructions per entry (one of them the exp) issued at 95% of the
+                     # 64 lane-ops/CU/cycle ceiling, which a 2-slot exp would put above 100%
 
 
 def sweep_peak_gentries(dim: int) -> float:
-    """FP32 exp/VALU roofline of one sweep entry: d FMAs + 1 add (weight) +
-    1 add (accumulate) + one exp2 at half rate, on 256 CUs x 64 lanes x 2.4 GHz."""
+    """FP32 exp/VALU roofline of one sweep entry, in Gentries/s: the fewest
+    VALU issue slots an entry can take in the tile-expanded form (d FMAs,
+    1 add of the weight, the exp2, 1 add into the sum) on 256 CUs x 64 lanes
+    x 2.4 GHz."""
     return CU * LANES * CLK / (dim + 2 + EXP_SLOTS) / 1e9
 
 

@@ -77,26 +77,20 @@ Layout make_layout(int m, int n, int dim, int reserve_row, int reserve_col) {
     return at;
   };
   L.ctrl = take(sizeof(Ctrl));
-  auto side = [&](const SideShape& s, size_t& abs, size_t& off, size_t& hdr, size_t& A, size_t& Amax,
-                  size_t& perm, size_t& marg, size_t& logm, size_t& iperm, size_t& hint, size_t& tfit,
-                  size_t& talpha) {
+  auto side = [&](const SideShape& s, size_t& abs, size_t& off, size_t& tile, size_t& A, size_t& perm,
+                  size_t& marg, size_t& logm, size_t& iperm, size_t& hint) {
     abs = take(sizeof(float) * (size_t)dim * s.np);
     off = take(sizeof(float) * (size_t)s.ntiles * dim * kTile);
-    hdr = take(sizeof(float) * (size_t)s.ntiles * kHdr);
+    tile = take(sizeof(TileRec) * (size_t)s.ntiles);
     A = take(sizeof(float) * (size_t)s.np);
-    Amax = take(sizeof(double) * (size_t)s.ntiles);
     perm = take(sizeof(int) * (size_t)s.np);
     marg = take(sizeof(double) * (size_t)s.np);
     logm = take(sizeof(double) * (size_t)s.np);
     iperm = take(sizeof(int) * (size_t)s.count);
     hint = take(sizeof(int) * (size_t)s.np);
-    tfit = take(sizeof(float) * 4 * (size_t)s.ntiles);
-    talpha = take(sizeof(double) * (size_t)s.ntiles);
   };
-  side(L.R, L.r_abs, L.r_off, L.r_hdr, L.r_A, L.r_Amax, L.r_perm, L.r_marg, L.r_logm, L.r_iperm, L.r_hint,
-       L.r_tfit, L.r_talpha);
-  side(L.C, L.c_abs, L.c_off, L.c_hdr, L.c_A, L.c_Amax, L.c_perm, L.c_marg, L.c_logm, L.c_iperm, L.c_hint,
-       L.c_tfit, L.c_talpha);
+  side(L.R, L.r_abs, L.r_off, L.r_tile, L.r_A, L.r_perm, L.r_marg, L.r_logm, L.r_iperm, L.r_hint);
+  side(L.C, L.c_abs, L.c_off, L.c_tile, L.c_A, L.c_perm, L.c_marg, L.c_logm, L.c_iperm, L.c_hint);
   L.la = take(sizeof(double) * L.R.np);
   L.lah = take(sizeof(double) * L.R.np);
   L.lb1 = take(sizeof(double) * L.C.np);
@@ -180,7 +174,8 @@ uint64_t spread2(uint64_t v) {
 }
 
 struct HostSide {
-  std::vector<float> abs, off, hdr;
+  std::vector<float> abs, off;
+  std::vector<TileRec> tile;
   std::vector<int> perm, iperm;
   std::vector<double> marg, logm;
 };
@@ -230,7 +225,10 @@ void build_side(const std::vector<float>& pts, const std::vector<double>& w, int
     hs.logm[s] = std::log(w[hs.perm[s]]);
   }
   hs.off.assign((size_t)sh.ntiles * dim * kTile, 0.f);
-  hs.hdr.assign((size_t)sh.ntiles * kHdr, 0.f);
+  TileRec blank{};
+  blank.amax = -INFINITY;
+  blank.alpha = -INFINITY;
+  hs.tile.assign((size_t)sh.ntiles, blank);
   for (int t = 0; t < sh.ntiles; ++t) {
     const int s0 = t * kTile, s1 = std::min(count, s0 + kTile);
     for (int d = 0; d < dim; ++d) {
@@ -246,8 +244,8 @@ void build_side(const std::vector<float>& pts, const std::vector<double>& w, int
         hs.off[((size_t)t * dim + d) * kTile + (s - s0)] = b;
         if (s < s1) rad = std::max(rad, std::fabs(b));
       }
-      hs.hdr[(size_t)t * kHdr + d] = ctr;
-      hs.hdr[(size_t)t * kHdr + 3 + d] = rad;
+      hs.tile[t].ctr[d] = ctr;
+      hs.tile[t].rad[d] = rad;
     }
   }
 }
@@ -263,30 +261,24 @@ void fill_ctx(bdrs_solver s) {
   c.splits_row = L.splits_row;
   c.splits_col = L.splits_col;
   c.ctrl = (Ctrl*)(base + L.ctrl);
-  auto side = [&](SideDev& sd, const SideShape& sh, size_t abs, size_t off, size_t hdr, size_t A, size_t Amax,
-                  size_t perm, size_t marg, size_t logm, size_t iperm, size_t hint, size_t tfit,
-                  size_t talpha) {
+  auto side = [&](SideDev& sd, const SideShape& sh, size_t abs, size_t off, size_t tile, size_t A, size_t perm,
+                  size_t marg, size_t logm, size_t iperm, size_t hint) {
     sd.count = sh.count;
     sd.ntiles = sh.ntiles;
     sd.np = sh.np;
     sd.pad = 0;
     sd.abs = (float*)(base + abs);
     sd.off = (float*)(base + off);
-    sd.hdr = (float*)(base + hdr);
+    sd.tile = (TileRec*)(base + tile);
     sd.A = (float*)(base + A);
-    sd.Amax = (double*)(base + Amax);
     sd.perm = (int*)(base + perm);
     sd.marg = (double*)(base + marg);
     sd.logmarg = (double*)(base + logm);
     sd.iperm = (int*)(base + iperm);
     sd.hint = (int*)(base + hint);
-    sd.tfit = (float*)(base + tfit);
-    sd.talpha = (double*)(base + talpha);
   };
-  side(c.rows, L.R, L.r_abs, L.r_off, L.r_hdr, L.r_A, L.r_Amax, L.r_perm, L.r_marg, L.r_logm, L.r_iperm, L.r_hint,
-       L.r_tfit, L.r_talpha);
-  side(c.cols, L.C, L.c_abs, L.c_off, L.c_hdr, L.c_A, L.c_Amax, L.c_perm, L.c_marg, L.c_logm, L.c_iperm, L.c_hint,
-       L.c_tfit, L.c_talpha);
+  side(c.rows, L.R, L.r_abs, L.r_off, L.r_tile, L.r_A, L.r_perm, L.r_marg, L.r_logm, L.r_iperm, L.r_hint);
+  side(c.cols, L.C, L.c_abs, L.c_off, L.c_tile, L.c_A, L.c_perm, L.c_marg, L.c_logm, L.c_iperm, L.c_hint);
   c.st.la = (double*)(base + L.la);
   c.st.lah = (double*)(base + L.lah);
   c.st.lb1 = (double*)(base + L.lb1);
@@ -756,7 +748,7 @@ bdrs_status create_from_host(const bdrs_params* p, const float* px, const float*
   };
   chk(up(c.rows.abs, R.abs.data(), R.abs.size() * sizeof(float)));
   chk(up(c.rows.off, R.off.data(), R.off.size() * sizeof(float)));
-  chk(up(c.rows.hdr, R.hdr.data(), R.hdr.size() * sizeof(float)));
+  chk(up(c.rows.tile, R.tile.data(), R.tile.size() * sizeof(TileRec)));
   chk(up(c.rows.perm, R.perm.data(), R.perm.size() * sizeof(int)));
   chk(up(c.rows.iperm, R.iperm.data(), R.iperm.size() * sizeof(int)));
   chk(up(c.cols.iperm, C.iperm.data(), C.iperm.size() * sizeof(int)));
@@ -766,7 +758,7 @@ bdrs_status create_from_host(const bdrs_params* p, const float* px, const float*
   chk(up(c.rows.logmarg, R.logm.data(), R.logm.size() * sizeof(double)));
   chk(up(c.cols.abs, C.abs.data(), C.abs.size() * sizeof(float)));
   chk(up(c.cols.off, C.off.data(), C.off.size() * sizeof(float)));
-  chk(up(c.cols.hdr, C.hdr.data(), C.hdr.size() * sizeof(float)));
+  chk(up(c.cols.tile, C.tile.data(), C.tile.size() * sizeof(TileRec)));
   chk(up(c.cols.perm, C.perm.data(), C.perm.size() * sizeof(int)));
   chk(up(c.cols.marg, C.marg.data(), C.marg.size() * sizeof(double)));
   chk(up(c.cols.logmarg, C.logm.data(), C.logm.size() * sizeof(double)));

@@ -29,8 +29,8 @@ struct Layout {
   size_t total;
   // offsets
   size_t ctrl;
-  size_t r_abs, r_off, r_hdr, r_A, r_Amax, r_perm, r_marg, r_logm, r_iperm, r_hint, r_tfit, r_talpha;
-  size_t c_abs, c_off, c_hdr, c_A, c_Amax, c_perm, c_marg, c_logm, c_iperm, c_hint, c_tfit, c_talpha;
+  size_t r_abs, r_off, r_tile, r_A, r_perm, r_marg, r_logm, r_iperm, r_hint;
+  size_t c_abs, c_off, c_tile, c_A, c_perm, c_marg, c_logm, c_iperm, c_hint;
   size_t la, lah, lb1, lb2, lbh, lt0, lt1, mu, logs, pvec;
   size_t part, cert_part, cert_out;
 };

@@ -15,7 +15,6 @@ constexpr int kBlock = 256;       // threads per block of the O(n) kernels
 #endif
 constexpr int kSweepBlock = BDRS_SWEEP_BLOCK;
 constexpr int kPad = kSweepBlock > kBlock ? kSweepBlock : kBlock;  // np is a multiple of this
-constexpr int kHdr = 8;           // floats per tile header: center[3], radius[3], pad[2]
 constexpr int kCertSlots = 16;    // doubles in a certificate record
 
 // (output wavefront, split) pairs a sweep aims for: 4 per SIMD on 256 CUs
@@ -32,6 +31,20 @@ struct Ctrl {
   double omega;
 };
 
+// Everything the sweep needs to know about one input tile besides the offsets
+// and weights of its points, read with a single 64-byte scalar load.
+struct alignas(64) TileRec {
+  double amax;    // tile maximum of the absolute log2 weights (float64; -inf: no mass)
+  double alpha;   // intercept of the plane fit of the tile's log2 weights w2 over the
+                  // offsets b: w2 <= alpha + gamma . b + rho for every point of the tile
+  float ctr[3];   // tile centre (relative to the common origin)
+  float rad[3];   // per-dimension radius of the offsets
+  float gam[3];   // plane-fit gradient gamma
+  float rho;      // largest residual of the fit, rounded up
+  float pad[2];
+};
+static_assert(sizeof(TileRec) == 64, "one scalar dwordx16 load per tile");
+
 // One point set stored in tile order.  Slot p holds original point perm[p];
 // slots >= count are padding (copies of a real point with weight -inf).
 struct SideDev {
@@ -41,13 +54,9 @@ struct SideDev {
   int pad;
   float* abs;      // [dim][np] coordinates relative to the common origin (SoA)
   float* off;      // [ntiles][dim][64] offsets from the tile centre
-  float* hdr;      // [ntiles][8] centre[3], per-dimension radius[3]
   float* A;        // [np] log2 weights of the next sweep that reads this side, relative
                    //      to their tile maximum (small magnitudes, float32)
-  double* Amax;    // [ntiles] tile maxima of the absolute log2 weights (float64)
-  float* tfit;     // [ntiles][4] plane fit of the tile's log2 weights w2 over the offsets b:
-                   //      gradient gamma[3] and the largest residual rho (float32)
-  double* talpha;  // [ntiles] intercept alpha of that fit (w2 <= alpha + gamma . b + rho)
+  TileRec* tile;   // [ntiles] per-tile record (maximum, plane fit, centre, radius)
   int* perm;       // [np] original index of each slot
   int* iperm;      // [count] slot of each original index
   int* hint;       // [np] warm start of the sweep with this side as output: the slot of an

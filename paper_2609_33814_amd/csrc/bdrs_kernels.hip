@@ -99,13 +99,67 @@ typedef __attribute__((address_space(1))) const float gfloat;
 typedef __attribute__((address_space(1))) const double gdouble;
 typedef __attribute__((address_space(1))) const Ctrl gctrl;
 
-// One block of 256 outputs (bx) against one split of the input tiles.
+typedef __attribute__((address_space(1))) const TileRec gtile;
+
+// Points of a tile per group: the tile data of one group (offsets and weights,
+// 8 (D + 1) floats) is loaded into scalar registers while the previous group
+// is being computed.
+constexpr int kGroup = 8;
+
+// The fields of a tile record the sweep uses (dimensions < D).
+template <int D>
+struct TileVals {
+  double amax, alpha;
+  float ctr[D], rad[D], gam[D], rho;
+};
+
+template <int D>
+__device__ __forceinline__ TileVals<D> load_tile(gtile* __restrict__ rec) {
+  gdouble* dp = (gdouble*)rec;
+  gfloat* fp = (gfloat*)rec;
+  TileVals<D> v;
+  v.amax = dp[0];
+  v.alpha = dp[1];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    v.ctr[d] = fp[4 + d];
+    v.rad[d] = fp[7 + d];
+    v.gam[d] = fp[10 + d];
+  }
+  v.rho = fp[13];
+  return v;
+}
+
+template <int D>
+struct Group {
+  float b[D][kGroup];
+  float a[kGroup];
+};
+
+template <int D>
+__device__ __forceinline__ Group<D> load_group(gfloat* __restrict__ in_off, gfloat* __restrict__ in_A, int t, int g) {
+  Group<D> r;
+  gfloat* offs = in_off + (size_t)t * D * kTile + g * kGroup;
+  gfloat* aq = in_A + (size_t)t * kTile + g * kGroup;
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) r.b[d][u] = offs[d * kTile + u];
+#pragma unroll
+  for (int u = 0; u < kGroup; ++u) r.a[u] = aq[u];
+  return r;
+}
+
+// One block of kSweepBlock outputs (bx) against one split of the input tiles.
+// The input side is streamed as tiles of 64 points; per tile the lane
+// evaluates z_q = cm + B . b_q + A'_q and accumulates exp2(z_q) (and, for the
+// certificate, the cost-weighted sum).  The next tile's record and the next
+// group of points are requested before the current group is computed, so the
+// scalar loads overlap the arithmetic.
 template <int D, bool CERT>
 __device__ __forceinline__ void sweep_block(
     gfloat* __restrict__ out_abs, int np_out,
-    gfloat* __restrict__ in_off, gfloat* __restrict__ in_hdr,
-    gfloat* __restrict__ in_A, gdouble* __restrict__ in_Amax,
-    gfloat* __restrict__ in_fit, gdouble* __restrict__ in_alpha,
+    gfloat* __restrict__ in_off, gfloat* __restrict__ in_A, gtile* __restrict__ in_tile,
     int ntiles_in, int count_in, int tps, const int* __restrict__ hint,
     PartialRec* __restrict__ part, gctrl* __restrict__ ctrl, double eps_arg, int kofs, int bx, int split) {
   const int p = bx * kSweepBlock + threadIdx.x;
@@ -131,13 +185,13 @@ __device__ __forceinline__ void sweep_block(
     const int j = hint[p];
     if (j >= 0 && j < count_in) {
       const int tj = j / kTile, qj = j % kTile;
-      const double am = in_Amax[tj];
+      const double am = in_tile[tj].amax;
       const float aj = in_A[j];
       if (am > -INFINITY && aj > -INFINITY) {
         double na = 0.0, ab = 0.0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          const double ad = (double)P[d] - (double)in_hdr[(size_t)tj * kHdr + d];
+          const double ad = (double)P[d] - (double)in_tile[tj].ctr[d];
           const double bd = (double)in_off[((size_t)tj * D + d) * kTile + qj];
           na += ad * ad;
           ab += ad * bd;
@@ -148,42 +202,49 @@ __device__ __forceinline__ void sweep_block(
     }
   }
   float S = 0.0f, N = 0.0f;
+  if (t0 >= t1) {
+    part[(size_t)split * np_out + p] = PartialRec{M, S, N, J, 0};
+    return;
+  }
 
+  TileVals<D> cur = load_tile<D>(in_tile + t0);
+  Group<D> grp = load_group<D>(in_off, in_A, t0, 0);
   for (int t = t0; t < t1; ++t) {
-    gfloat* __restrict__ hdr = in_hdr + (size_t)t * kHdr;
-    const double amax = in_Amax[t];
-    if (amax == -INFINITY) continue;  // tile carries no mass (masked weights)
+    const int tn = min(t + 1, t1 - 1);         // next tile (the last one re-reads itself)
+    if (cur.amax == -INFINITY) {               // tile carries no mass (masked weights)
+      cur = load_tile<D>(in_tile + tn);
+      grp = load_group<D>(in_off, in_A, tn, 0);
+      continue;
+    }
     float a[D], B[D], na = 0.0f;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      a[d] = P[d] - hdr[d];
+      a[d] = P[d] - cur.ctr[d];
       na = fmaf(a[d], a[d], na);
       B[d] = kap2x2 * a[d];
     }
-    const double base = amax - kap2d * (double)na;  // Amax_t - kappa2 |a|^2
+    const double base = cur.amax - kap2d * (double)na;  // Amax_t - kappa2 |a|^2
     // upper bound of the exponents w2_q - kappa2 |a - b_q|^2 of this tile:
     // w2_q <= alpha + gamma . b_q + rho, and the concave quadratic
     // gamma . b - kappa2 |a - b|^2 is maximised over the tile's box per axis
-    gfloat* __restrict__ fit = in_fit + (size_t)t * 4;
-    float ubf = fit[3];
+    float ubf = cur.rho;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      const float g = fit[d], rad = hdr[3 + d];
+      const float g = cur.gam[d], rad = cur.rad[d];
       const float bs = fminf(fmaxf(fmaf(g, inv2kap, a[d]), -rad), rad);
       const float df = a[d] - bs;
       ubf = fmaf(g, bs, ubf);
       ubf = fmaf(-kap2f, df * df, ubf);
     }
-    const double ub = in_alpha[t] + (double)ubf;
-
-    gfloat* __restrict__ offs = in_off + (size_t)t * D * kTile;
-    gfloat* __restrict__ Aq = in_A + (size_t)t * kTile;
+    const double ub = cur.alpha + (double)ubf;
 
     if (ub > M + kThresh) {
       // exact maximum of this tile for the lanes whose bound exceeds the window
+      gfloat* __restrict__ offs = in_off + (size_t)t * D * kTile;
+      gfloat* __restrict__ Aq = in_A + (size_t)t * kTile;
       float tm = -INFINITY;
       int qi = 0;
-#pragma unroll 16
+#pragma unroll 8
       for (int q = 0; q < kTile; ++q) {
         float z = Aq[q];
 #pragma unroll
@@ -203,35 +264,41 @@ __device__ __forceinline__ void sweep_block(
       }
     }
     const float cm = (float)(base - M);
+    const TileVals<D> nxt = load_tile<D>(in_tile + tn);
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
     float n0 = 0.f, n1 = 0.f;
-#pragma unroll 16
-    for (int q = 0; q < kTile; q += 4) {
-      float e[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+    for (int g = 0; g < kTile / kGroup; ++g) {
+      // request the next group (the first group of the next tile after the last)
+      const Group<D> nx = (g + 1 < kTile / kGroup) ? load_group<D>(in_off, in_A, t, g + 1)
+                                                  : load_group<D>(in_off, in_A, tn, 0);
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) {
         float z = cm;
 #pragma unroll
-        for (int d = 0; d < D; ++d) z = fmaf(B[d], offs[d * kTile + q + u], z);
-        z += Aq[q + u];
-        e[u] = fast_exp2(z);
+        for (int d = 0; d < D; ++d) z = fmaf(B[d], grp.b[d][u], z);
+        z += grp.a[u];
+        const float e = fast_exp2(z);
+        if (g == 0 && u < 4) {
+          (u == 0 ? s0 : u == 1 ? s1 : u == 2 ? s2 : s3) = e;
+        } else {
+          (u % 4 == 0 ? s0 : u % 4 == 1 ? s1 : u % 4 == 2 ? s2 : s3) += e;
+        }
         if (CERT) {
           float c2 = 0.0f;
 #pragma unroll
           for (int d = 0; d < D; ++d) {
-            const float df = a[d] - offs[d * kTile + q + u];
+            const float df = a[d] - grp.b[d][u];
             c2 = fmaf(df, df, c2);
           }
-          if (u & 1) n1 = fmaf(c2, e[u], n1); else n0 = fmaf(c2, e[u], n0);
+          if (u & 1) n1 = fmaf(c2, e, n1); else n0 = fmaf(c2, e, n0);
         }
       }
-      s0 += e[0];
-      s1 += e[1];
-      s2 += e[2];
-      s3 += e[3];
+      grp = nx;
     }
     S += (s0 + s1) + (s2 + s3);
     if (CERT) N += n0 + n1;
+    cur = nxt;
   }
   PartialRec rec;
   rec.M = M;
@@ -245,14 +312,11 @@ __device__ __forceinline__ void sweep_block(
 template <int D, bool CERT>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(
     const float* __restrict__ out_abs, int np_out,
-    const float* __restrict__ in_off, const float* __restrict__ in_hdr,
-    const float* __restrict__ in_A, const double* __restrict__ in_Amax,
-    const float* __restrict__ in_fit, const double* __restrict__ in_alpha,
+    const float* __restrict__ in_off, const float* __restrict__ in_A, const TileRec* __restrict__ in_tile,
     int ntiles_in, int count_in, int tps, const int* __restrict__ hint,
     PartialRec* __restrict__ part, const Ctrl* __restrict__ ctrl, double eps_arg, int kofs) {
-  sweep_block<D, CERT>((gfloat*)out_abs, np_out, (gfloat*)in_off, (gfloat*)in_hdr, (gfloat*)in_A,
-                       (gdouble*)in_Amax, (gfloat*)in_fit, (gdouble*)in_alpha, ntiles_in, count_in, tps, hint,
-                       part, (gctrl*)ctrl, eps_arg, kofs, blockIdx.x, blockIdx.y);
+  sweep_block<D, CERT>((gfloat*)out_abs, np_out, (gfloat*)in_off, (gfloat*)in_A, (gtile*)in_tile, ntiles_in,
+                       count_in, tps, hint, part, (gctrl*)ctrl, eps_arg, kofs, blockIdx.x, blockIdx.y);
 }
 
 // Batched sweep: block i runs work item i = (problem, block of outputs, split)
@@ -268,9 +332,8 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep_batch(const BatchItem* __
   const SideDev& in = transpose ? c.rows : c.cols;
   const int splits = transpose ? c.splits_col : c.splits_row;
   const int tps = (in.ntiles + splits - 1) / splits;
-  sweep_block<D, CERT>((gfloat*)out.abs, out.np, (gfloat*)in.off, (gfloat*)in.hdr, (gfloat*)in.A,
-                       (gdouble*)in.Amax, (gfloat*)in.tfit, (gdouble*)in.talpha, in.ntiles, in.count, tps,
-                       out.hint, c.part.rec, (gctrl*)c.ctrl, -1.0, kofs, it.blk, it.split);
+  sweep_block<D, CERT>((gfloat*)out.abs, out.np, (gfloat*)in.off, (gfloat*)in.A, (gtile*)in.tile, in.ntiles,
+                       in.count, tps, out.hint, c.part.rec, (gctrl*)c.ctrl, -1.0, kofs, it.blk, it.split);
 }
 
 // ---------------------------------------------------------------------------
@@ -413,11 +476,11 @@ __device__ __forceinline__ void pack_weight_d(const SideDev& sd, int p, double w
   }
   const double rho = wave_max(fabs(res));
   if ((threadIdx.x & (kTile - 1)) == 0) {
-    sd.Amax[t] = m;
-    sd.talpha[t] = alpha;
-    float* f = sd.tfit + (size_t)t * 4;
-    for (int d = 0; d < 3; ++d) f[d] = (float)gam[d];
-    f[3] = (float)(rho * (1.0 + 1e-6)) + 1e-3f;  // rounded up: the bound must hold
+    TileRec& tr = sd.tile[t];
+    tr.amax = m;
+    tr.alpha = alpha;
+    for (int d = 0; d < 3; ++d) tr.gam[d] = (float)gam[d];
+    tr.rho = (float)(rho * (1.0 + 1e-6)) + 1e-3f;  // rounded up: the bound must hold
   }
 }
 
@@ -829,7 +892,7 @@ hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int split
   dim3 grid(out.np / kSweepBlock, splits);
 #define BDRS_SWEEP(DD, CC)                                                                          \
   hipLaunchKernelGGL((k_sweep<DD, CC>), grid, dim3(kSweepBlock), 0, c.stream, out.abs, out.np, in.off,  \
-                     in.hdr, in.A, in.Amax, in.tfit, in.talpha, in.ntiles, in.count, tps, out.hint,      \
+                     in.A, in.tile, in.ntiles, in.count, tps, out.hint,                                  \
                      c.part.rec, c.ctrl, eps_arg, kofs)
   switch (c.dim * 2 + (cert ? 1 : 0)) {
     case 2: BDRS_SWEEP(1, false); break;

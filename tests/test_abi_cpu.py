@@ -29,7 +29,8 @@ def test_library_exports_every_declared_symbol():
     assert bdrs.lib().bdrs_version().decode().startswith("bdrs")
 
 
-def test_workspace_is_linear_in_points():
+def test_workspace_is_linear_in_points(saved_table):
+    # heuristic split counts (the tuning table is emptied by the fixture)
     a = bdrs.workspace_size(1024, 1024, 2)
     b = bdrs.workspace_size(16384, 16384, 2)
     c = bdrs.workspace_size(1 << 20, 1 << 20, 3)

@@ -145,9 +145,15 @@ def test_c1_trajectory_parity(c1_oracle):
     assert gs["k"] == 500
 
 
-def test_certificate_from_identical_state(c1_oracle):
+@pytest.mark.parametrize("k", [9, 199])
+def test_certificate_from_identical_state(c1_oracle, k):
+    """delta = 1/2 sum_j |s_j - c_j| inherits the relative float32 error of each
+    s_j (a sweep output): |d delta| <= 1/2 sum_j s_j |ds_j / s_j| <= 1/2 max_j
+    |ds_j / s_j|, and the float32 exponent-rounding model (absolute log error
+    ~ u |g| / eps plus the summation error ~ sqrt(n) u) bounds that by ~4e-6
+    here (eps >= 5e-3, n = 1024), hence the absolute 2e-6 next to the
+    relative 1e-4 that applies while delta is large."""
     prob, _, _, states = c1_oracle
-    k = 199
     st = states[k]
     d = dev()
     T = lambda a: torch.as_tensor(a, device=d)
@@ -162,7 +168,7 @@ def test_certificate_from_identical_state(c1_oracle):
     assert ce["k"] == k
     assert abs(ce["L"] - ref["L"]) <= 1e-9 * abs(ref["L"])
     assert abs(ce["U"] - ref["U"]) <= 1e-5 * abs(ref["U"])
-    assert abs(ce["delta"] - ref["delta"]) <= 1e-4 * ref["delta"] + 1e-9
+    assert abs(ce["delta"] - ref["delta"]) <= 1e-4 * ref["delta"] + 2e-6
     assert ce["n_nonfinite"] == 0
 
 
