@@ -34,6 +34,28 @@ EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters
                      # 64 lane-ops/CU/cycle ceiling, which a 2-slot exp would put above 100%
 
 
+# HBM traffic of one k_sweep<2,false> launch on the 128x128 grids (16 splits per
+# direction): rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE per dispatch, each scaled
+# by what the counter reads for a 256 MiB device copy (x2.000 and x1.000).  It
+# holds for the kernel source with this sha256 only; otherwise it is reported
+# as null.
+TRAFFIC_KERNEL_SHA256 = "2a2900027faad2a8e829bb0f88fb312ec67ef234c10b706d8fa3bf0e01685190"
+TRAFFIC_SPLITS = 16
+TRAFFIC_BYTES_PER_LAUNCH = 9.62e6
+
+
+def measured_traffic(splits_row: int):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2609_33814_amd", "csrc", "bdrs_kernels.hip")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if sha != TRAFFIC_KERNEL_SHA256 or splits_row != TRAFFIC_SPLITS:
+        return None
+    return TRAFFIC_BYTES_PER_LAUNCH
+
+
 def sweep_peak_gentries(dim: int) -> float:
     """FP32 exp/VALU roofline of one sweep entry, in Gentries/s: the fewest
     VALU issue slots an entry can take in the tile-expanded form (d FMAs,
@@ -42,8 +64,20 @@ def sweep_peak_gentries(dim: int) -> float:
     return CU * LANES * CLK / (dim + 2 + EXP_SLOTS) / 1e9
 
 
+def _oracle_rows(task):
+    """One block of sampled output rows of the oracle's row sweep (pool worker)."""
+    from oracle import lse
+    x, y, scale, w, rows = task
+    lse.implicit_lse(x, y, scale, 0.01, w, rows=rows)
+    return rows.size
+
+
 def cpu_baseline(prob, seconds: float = 12.0) -> dict:
-    """The FP64 oracle's LSE sweep on sampled output rows, timed on the host."""
+    """The FP64 oracle's LSE sweep on sampled output rows, timed on the host:
+    first in this process (one thread), then with a fork pool of worker
+    processes over blocks of rows, one per core of this process's CPU share
+    (at most 16).  Runs before the GPU is touched, so forking is safe."""
+    import multiprocessing as mp
     import numpy as np
     from oracle import lse
     rng = np.random.default_rng(0)
@@ -57,9 +91,20 @@ def cpu_baseline(prob, seconds: float = 12.0) -> dict:
         done += rows_per_call
     dt = time.perf_counter() - t0
     entries = done * prob.n
-    return {"value": entries / dt / 1e9, "unit": "Gentries/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} random output rows x {prob.n} columns of the row sweep "
-                      f"({entries:.3g} entries, {dt:.1f} s, numpy FP64, one thread)"}
+    one = entries / dt / 1e9
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    tasks = [(prob.x, prob.y, prob.cost_scale, w, rng.choice(prob.m, rows_per_call, replace=False))
+             for _ in range(int(one * 1e9 * seconds * cores / (rows_per_call * prob.n)) + cores)]
+    with mp.get_context("fork").Pool(cores) as pool:
+        t1 = time.perf_counter()
+        done_all = sum(pool.imap_unordered(_oracle_rows, tasks))
+        dt_all = time.perf_counter() - t1
+    entries_all = done_all * prob.n
+    return {"value": entries_all / dt_all / 1e9, "unit": "Gentries/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done_all} random output rows x {prob.n} columns of the row sweep "
+                      f"({entries_all:.3g} entries, {dt_all:.1f} s, numpy FP64, {cores} worker processes)",
+            "single_thread": {"value": one, "cores": 1,
+                              "sample": f"{done} rows x {prob.n} columns ({entries:.3g} entries, {dt:.1f} s)"}}
 
 
 def batch_mode(args) -> int:
@@ -123,8 +168,8 @@ def batch_mode(args) -> int:
 
 
 def serve_mode(args) -> int:
-    """Poisson arrivals of grid OT requests (sides from {32, 64, 128}, drawn with
-    seed 52; inter-arrival gaps with seed 51; request q seeds (5100+2q, 5101+2q)),
+    """Poisson arrivals of grid OT requests (sides from --serve-sides, default
+    {32, 64, 128}, drawn with seed 52; inter-arrival gaps with seed 51; request q seeds (5100+2q, 5101+2q)),
     each stopped at a 1% relative gap.  The arrival rate is `load` times the
     sequential capacity measured on a sample.  The same arrival schedule is
     served twice: one request at a time (FIFO) and with continuous batching
@@ -134,7 +179,7 @@ def serve_mode(args) -> int:
     import torch
     from paper_2609_33814_amd import bdrs, inputs
     n_req = args.requests
-    menu = [32, 64, 128]
+    menu = [int(v) for v in args.serve_sides.split(",")]
     sides = [menu[i] for i in np.random.default_rng(52).integers(0, len(menu), n_req)]
     probs = [inputs.grid_problem(s, 5100 + 2 * q, 5101 + 2 * q) for q, s in enumerate(sides)]
     tau, cap, block, pool = 0.01, 20000, CERT_EVERY, 1 << 30
@@ -314,6 +359,7 @@ def main() -> int:
                          "arrivals, FIFO one-at-a-time vs continuous batching; colour: 1M-point "
                          "colour transfer; colour10m: 10M points, per-iteration time")
     ap.add_argument("--colour-iters", type=int, default=100)
+    ap.add_argument("--serve-sides", default="32,64,128", help="grid sides of the serve requests")
     ap.add_argument("--requests", type=int, default=96)
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate / sequential capacity")
     ap.add_argument("--calib-copy", action="store_true",
@@ -329,6 +375,12 @@ def main() -> int:
     import torch
     from paper_2609_33814_amd import bdrs, inputs
 
+    if args.mode == "sweep" and not args.no_cpu:
+        cpu = cpu_baseline(inputs.c2_problem())   # before the GPU is first used
+        print(f"[bench] oracle on the host: {cpu['value']:.3f} Gentries/s on {cpu['cores']} cores, "
+              f"{cpu['single_thread']['value']:.3f} on one", flush=True)
+    else:
+        cpu = None
     dev = torch.device("cuda:0")
     if args.mode == "batch":
         return batch_mode(args)
@@ -345,6 +397,8 @@ def main() -> int:
     print(f"[bench] workload grid128x128 m=n={prob.m} eta={ETA} lambda={args.lam}", flush=True)
 
     sv = bdrs.Solver(X, Y, R, C, prob.cost_scale, eta=ETA, lam=args.lam)
+    tuned = [e for e in bdrs.tune_table() if (e["dim"], e["m"], e["n"]) == (prob.dim, prob.m, prob.n)]
+    splits_row = tuned[0]["splits_row"] if tuned else None
     for _ in range(args.warmup):
         sv.solve(0.0, CERT_EVERY, CERT_EVERY)
     torch.cuda.synchronize()
@@ -392,7 +446,6 @@ def main() -> int:
         print("[bench] calibration copy: 268435456 bytes read, 268435456 bytes written", flush=True)
         del src, dst
 
-    cpu = None if args.no_cpu else cpu_baseline(prob)
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "Gentries/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4),
@@ -404,8 +457,10 @@ def main() -> int:
                    "step": "50 iterations (100 sweeps) + fused certificate",
                    "last_rel_gap": last["rel_gap"] if last else None},
         "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 2),
-                     "unit": "Gentries/s", "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": "k_sweep<2,false>", "per_launch_us": round(per_sweep_ms * 1e3, 3)},
+                     "unit": "Gentries/s", "frac": round(achieved / peak, 4),
+                     "traffic": measured_traffic(splits_row), "traffic_unit": "HBM bytes per launch",
+                     "kernel": "k_sweep<2,false>", "per_launch_us": round(per_sweep_ms * 1e3, 3),
+                     "splits": splits_row},
         "cpu_baseline": cpu,
         "time_to_1pct": ttg,
     }
