@@ -15,9 +15,11 @@ Modules (each function cites the passage of the paper it follows):
 * ``primal``       primal-plan BDRS (Eq. 3), O-BDRS (Sec. 3.3) and IPOT with L
                    inner Sinkhorn steps, in the linear domain, dense, for pins
 * ``lp``           exact LP optima used to bracket the certificate
+* ``plan``         the state plan's marginals, marginal-error statistics and
+                   barycentric projection (colour-transfer outputs)
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test
 against something other than itself (identities of the paper, exact LP
 optima, closed forms, brute force).  No function is "parity unpinned".
 """
-from . import lse, alg1, certificate, repair, primal, lp  # noqa: F401
+from . import lse, alg1, certificate, repair, primal, lp, plan  # noqa: F401

@@ -13,7 +13,7 @@ import mpmath
 import numpy as np
 import pytest
 
-from oracle import alg1, certificate, lp, lse, primal, repair
+from oracle import alg1, certificate, lp, lse, plan, primal, repair
 from paper_2609_33814_amd import inputs
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -297,3 +297,67 @@ def test_generators_are_valid_problems():
     q = inputs.colour_problem(3000, 2000, 31, 32)
     C = lse.cost_matrix(q.x, q.y, q.cost_scale)
     assert abs(C.max() - 1.0) < 1e-12 and C.min() >= 0
+
+
+# ----------------------------------------------------------------------------
+# State plan: marginals, marginal-error statistics, barycentric projection
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("lam", [1.0, 1.5, 1.99])
+def test_plan_outputs_equal_dense_primal_plan(lam):
+    """Row / column sums and barycentric projection of the implicit state plan
+    (from the dual scalings alpha^{K-1}, beta^{K-1} and the kernel power
+    lambda K) equal those of the primal O-BDRS plan X^K built densely by the
+    primal update of Sec. 3.3 (BDRS for lambda = 1)."""
+    p = small_problem(9, 12, 3, 21)
+    eta, K = 0.8, 40
+    C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+    X = primal.obdrs_primal(C, p.r, p.c, eta, lam, K)[0][K]
+    st, _, _ = alg1.run(p, eta, lam, K)
+    eps = plan.plan_temperature(eta, lam, st.k)
+    row = plan.row_marginal(p.x, p.y, p.cost_scale, eps, st.la, st.lb1)
+    col = plan.col_marginal(p.x, p.y, p.cost_scale, eps, st.la, st.lb1)
+    bary = plan.barycentric(p.x, p.y, p.cost_scale, eps, st.lb1)
+    assert np.allclose(row, X.sum(axis=1), rtol=1e-10, atol=0)
+    assert np.allclose(col, X.sum(axis=0), rtol=1e-10, atol=0)
+    ref = (X @ p.y.astype(np.float64)) / X.sum(axis=1)[:, None]
+    assert np.allclose(bary, ref, rtol=1e-10, atol=1e-12)
+    stats = plan.marginal_stats(row, col, p.r, p.c)
+    assert abs(stats["mass"] - X.sum()) < 1e-12
+    assert abs(stats["row_l1"] - np.abs(X.sum(axis=1) - p.r).sum()) < 1e-12
+
+
+def test_bdrs_state_plan_has_column_marginal_c():
+    """For lambda = 1 the column sums of X^{k+1} are c by construction (Sec. 2:
+    b^k = c / (K^{.(k+1)})^T a^k)."""
+    p = inputs.grid_problem(12, 3, 4)
+    st, _, _ = alg1.run(p, 0.5, 1.0, 30)
+    eps = plan.plan_temperature(0.5, 1.0, st.k)
+    col = plan.col_marginal(p.x, p.y, p.cost_scale, eps, st.la, st.lb1)
+    assert np.allclose(col, p.c, rtol=1e-12, atol=0)
+    row = plan.row_marginal(p.x, p.y, p.cost_scale, eps, st.la, st.lb1)
+    assert abs(row.sum() - 1.0) < 1e-12          # same total mass
+    assert np.abs(row - p.r).max() > 1e-9          # the row marginal is not yet r
+
+
+def test_barycentric_special_cases():
+    rng = np.random.default_rng(3)
+    x = rng.random((30, 3)).astype(np.float32)
+    # one target point: every projection is that point
+    y1 = np.array([[0.25, 0.5, 0.75]], dtype=np.float32)
+    b = plan.barycentric(x, y1, 1.0, 0.05, np.zeros(1))
+    assert np.allclose(b, np.broadcast_to(y1.astype(np.float64), b.shape), rtol=0, atol=1e-15)
+    # a zero cost scale makes every kernel entry 1: the projection is the
+    # beta-weighted mean of the targets
+    y = rng.random((17, 3)).astype(np.float32)
+    lb = rng.normal(0, 1, 17)
+    b = plan.barycentric(x, y, 0.0, 1.0, lb)
+    w = np.exp(lb) / np.exp(lb).sum()
+    assert np.allclose(b, np.broadcast_to(w @ y.astype(np.float64), b.shape), rtol=1e-13, atol=1e-15)
+
+
+def test_marginal_stats_by_hand():
+    st = plan.marginal_stats([0.6, 0.4], [0.5, 0.5], [0.5, 0.5], [0.25, 0.75])
+    assert st["row_l1"] == pytest.approx(0.2) and st["row_max_abs"] == pytest.approx(0.1)
+    assert st["row_max_rel"] == pytest.approx(0.2)
+    assert st["col_l1"] == pytest.approx(0.5) and st["col_max_abs"] == pytest.approx(0.25)
+    assert st["col_max_rel"] == pytest.approx(1.0) and st["mass"] == pytest.approx(1.0)
