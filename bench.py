@@ -284,6 +284,11 @@ def colour_mode(args) -> int:
     achieved = prob.m * prob.n / (per_sweep_ms * 1e-3) / 1e9
     peak = sweep_peak_gentries(prob.dim)
     value = 2.0 * prob.m * prob.n * iters / wall / 1e9
+    # the state plan of the last iterate: marginal errors and barycentric projection
+    t1 = time.perf_counter()
+    pl = sv.plan()
+    plan_s = time.perf_counter() - t1
+    print(f"[bench] state plan: {plan_s:.2f} s, {pl['stats']}", flush=True)
     line = {
         "metric": "Gentries/s of fused LSE sweeps (colour transfer)", "value": round(value, 2),
         "unit": "Gentries/s", "n_gpus": 1, "steps": iters, "higher_is_better": True, "dtype": "f32",
@@ -296,6 +301,7 @@ def colour_mode(args) -> int:
                      "unit": "Gentries/s", "frac": round(achieved / peak, 4), "traffic": None,
                      "kernel": "k_sweep<3,false>", "per_launch_us": round(per_sweep_ms * 1e3, 3)},
         "time_to_1pct": reached_at, "trajectory": traj,
+        "state_plan": {"seconds": round(plan_s, 3), **pl["stats"]},
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -191,6 +191,37 @@ BDRS_API bdrs_status bdrs_lse(bdrs_solver s, int32_t transpose, double eps,
                      const double *w, double *out);
 
 /*
+ * The state plan after k >= 1 finished iterations,
+ *   X^k = diag(alpha^{k-1}) K^{.lambda k} diag(beta^{k-1}),  K = exp(-C / eta)
+ * (the O-BDRS state of Prop. 2; for lambda = 1 the BDRS plan of Lemma 1,
+ * whose column sums are c), and what the colour-transfer experiments read
+ * from it: its row and column sums, their errors against r and c, and the
+ * barycentric projection y^_i = sum_j X_ij y_j / sum_j X_ij of every source
+ * point onto the target points.  X is never formed: one row sweep at
+ * temperature eta / (lambda k) on the weights log beta^{k-1} that also
+ * accumulates the target coordinates, and one column sweep on log alpha^{k-1}
+ * (float32 sweeps, float64 merges and sums).
+ */
+typedef struct {
+  int64_t k;                      /* finished iterations (the plan is X^k) */
+  double eps;                     /* temperature of its kernel, eta / (lambda k) */
+  double row_l1, col_l1;          /* sum_i |(X 1)_i - r_i|,  sum_j |(X^T 1)_j - c_j| */
+  double row_max_abs, col_max_abs;/* largest absolute marginal error */
+  double row_max_rel, col_max_rel;/* largest error relative to r_i (c_j) */
+  double mass;                    /* 1^T X 1 */
+} bdrs_plan_stats;
+
+/* Evaluates the state plan of the solver's current iterate.  Optional
+ * outputs (NULL skips, device memory, original point order): bary m x dim
+ * row-major float64 (in the caller's coordinates), row_marg m float64,
+ * col_marg n float64; stats (host, optional).  BDRS_E_STATE before the first
+ * iteration.  Uses the solver's sweep buffers, not its dual state or warm-
+ * start hints, so the iteration that follows is unchanged.  Synchronises the
+ * stream. */
+BDRS_API bdrs_status bdrs_plan(bdrs_solver s, double *bary, double *row_marg, double *col_marg,
+                               bdrs_plan_stats *stats);
+
+/*
  * Batched solving (many independent problems in one set of launches).
  * The problems are solver objects from bdrs_create (each with its own
  * workspace), all with the same dim, all at an iteration count that is a

@@ -27,7 +27,7 @@ EXPORTS = [
     "bdrs_batch_solve", "bdrs_server_create", "bdrs_server_submit", "bdrs_server_poll",
     "bdrs_server_wait", "bdrs_server_stats", "bdrs_server_now", "bdrs_server_destroy",
     "bdrs_get_hints", "bdrs_set_hints", "bdrs_autotune_workspace_size", "bdrs_autotune",
-    "bdrs_tune_set", "bdrs_tune_get", "bdrs_tune_clear",
+    "bdrs_tune_set", "bdrs_tune_get", "bdrs_tune_clear", "bdrs_plan",
 ]
 
 
@@ -78,6 +78,19 @@ class Result(ctypes.Structure):
     def as_dict(self) -> dict:
         return dict(state=self.state, status=self.status, cert=self.cert.as_dict(),
                     t_submit=self.t_submit, t_admit=self.t_admit, t_done=self.t_done)
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int64), ("eps", ctypes.c_double),
+        ("row_l1", ctypes.c_double), ("col_l1", ctypes.c_double),
+        ("row_max_abs", ctypes.c_double), ("col_max_abs", ctypes.c_double),
+        ("row_max_rel", ctypes.c_double), ("col_max_rel", ctypes.c_double),
+        ("mass", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class TuneEntry(ctypes.Structure):
@@ -141,6 +154,7 @@ def lib() -> ctypes.CDLL:
         L.bdrs_tune_set.argtypes = [P(TuneEntry)]
         L.bdrs_tune_get.argtypes = [ctypes.c_int32, P(TuneEntry), P(ctypes.c_int32)]
         L.bdrs_tune_clear.argtypes = []
+        L.bdrs_plan.argtypes = [vp, vp, vp, vp, P(PlanStats)]
         L.bdrs_last_error.restype = ctypes.c_char_p
         L.bdrs_version.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -262,6 +276,18 @@ class Solver:
         out = torch.empty(self.n if transpose else self.m, dtype=torch.float64, device=w.device)
         check(lib().bdrs_lse(self._h, 1 if transpose else 0, float(eps), _ptr(w), _ptr(out)))
         return out
+
+    def plan(self, bary: bool = True, marginals: bool = True) -> dict:
+        """State plan of the current iterate: stats, and (optionally) the
+        barycentric projection (m, dim) and the row / column sums (float64)."""
+        torch = self._torch
+        dev = self._inputs[0].device
+        b = torch.empty((self.m, self.dim), dtype=torch.float64, device=dev) if bary else None
+        rm = torch.empty(self.m, dtype=torch.float64, device=dev) if marginals else None
+        cm = torch.empty(self.n, dtype=torch.float64, device=dev) if marginals else None
+        st = PlanStats()
+        check(lib().bdrs_plan(self._h, _ptr(b), _ptr(rm), _ptr(cm), ctypes.byref(st)))
+        return dict(stats=st.as_dict(), bary=b, row=rm, col=cm)
 
     def profile(self, enable: bool) -> None:
         check(lib().bdrs_profile(self._h, 1 if enable else 0))

@@ -103,6 +103,9 @@ Layout make_layout(int m, int n, int dim, int reserve_row, int reserve_col) {
   L.pvec = take(sizeof(double) * L.R.np);
   L.cert_part = take(sizeof(double) * 2 * (size_t)L.cert_blocks * 8);
   L.cert_out = take(sizeof(double) * kCertSlots);
+  L.plan_row = take(sizeof(double) * L.R.np);
+  L.plan_col = take(sizeof(double) * L.C.np);
+  L.plan_stats = take(sizeof(double) * kCertSlots);
   // partial records last: every other offset is independent of the split counts
   const size_t rows_rec = (size_t)std::max(L.splits_row, reserve_row) * L.R.np;
   const size_t cols_rec = (size_t)std::max(L.splits_col, reserve_col) * L.C.np;
@@ -294,6 +297,9 @@ void fill_ctx(bdrs_solver s) {
   c.cert_part = (double*)(base + L.cert_part);
   c.cert_out = (double*)(base + L.cert_out);
   c.cert_blocks = L.cert_blocks;
+  c.plan_row = (double*)(base + L.plan_row);
+  c.plan_col = (double*)(base + L.plan_col);
+  c.plan_stats = (double*)(base + L.plan_stats);
 }
 
 // reads the device iteration counter (synchronises the stream)
@@ -734,6 +740,7 @@ bdrs_status create_from_host(const bdrs_params* p, const float* px, const float*
     for (int j = 0; j < n; ++j) lo = std::min(lo, (double)hy[(size_t)j * dim + d]), hi = std::max(hi, (double)hy[(size_t)j * dim + d]);
     origin[d] = (double)(float)(0.5 * (lo + hi));
   }
+  for (int d = 0; d < 3; ++d) s->ctx.origin[d] = d < dim ? origin[d] : 0.0;
   HostSide R, C;
   build_side(hx, hr, m, dim, origin, s->L.R, R);
   build_side(hy, hc, n, dim, origin, s->L.C, C);
@@ -939,6 +946,47 @@ bdrs_status bdrs_lse(bdrs_solver s, int32_t transpose, double eps, const double*
   if (st != BDRS_OK) return st;
   if ((e = sweep(s, tr, false, splits, eps)) != hipSuccess) return hip_status(e, "sweep");
   if ((e = launch_finish(c, tr, kFinishLse, splits, eps, out, 0)) != hipSuccess) return hip_status(e, "finish");
+  s->packed_rows = false;
+  return repack(s);
+}
+
+bdrs_status bdrs_plan(bdrs_solver s, double* bary, double* row_marg, double* col_marg, bdrs_plan_stats* out) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  bdrs_status st = sync_k(s);
+  if (st != BDRS_OK) return st;
+  if (s->k < 1) return fail(BDRS_E_STATE, "the state plan needs at least one finished iteration");
+  const LaunchCtx& c = s->ctx;
+  // X^k = diag(alpha^{k-1}) K^{.lambda k} diag(beta^{k-1}): kernel temperature eta / (lambda k)
+  const double eps = s->prm.eta / (s->prm.lambda * (double)s->k);
+  hipError_t e;
+  if ((e = launch_pack_state(c, false, eps)) != hipSuccess) return hip_status(e, "pack beta");
+  if ((e = launch_sweep_bary(c, s->L.splits_row, eps)) != hipSuccess) return hip_status(e, "row sweep");
+  if ((e = launch_finish(c, false, kFinishPlanRow, s->L.splits_row, eps, bary, 0)) != hipSuccess)
+    return hip_status(e, "row finish");
+  if ((e = launch_pack_state(c, true, eps)) != hipSuccess) return hip_status(e, "pack alpha");
+  if ((e = sweep(s, true, false, s->L.splits_col, eps)) != hipSuccess) return hip_status(e, "column sweep");
+  if ((e = launch_finish(c, true, kFinishPlanCol, s->L.splits_col, eps, nullptr, 0)) != hipSuccess)
+    return hip_status(e, "column finish");
+  if ((e = launch_plan_stats(c)) != hipSuccess) return hip_status(e, "statistics");
+  // tile order -> caller order
+  if (row_marg && (e = launch_scatter(c.plan_row, c.rows.perm, c.rows.count, row_marg, c.stream)) != hipSuccess)
+    return hip_status(e, "row scatter");
+  if (col_marg && (e = launch_scatter(c.plan_col, c.cols.perm, c.cols.count, col_marg, c.stream)) != hipSuccess)
+    return hip_status(e, "column scatter");
+  double h[kCertSlots];
+  HIPCHK(hipMemcpyAsync(h, c.plan_stats, sizeof(double) * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  if (out) {
+    out->k = s->k;
+    out->eps = eps;
+    out->row_l1 = h[0];
+    out->row_max_abs = h[1];
+    out->row_max_rel = h[2];
+    out->col_l1 = h[3];
+    out->col_max_abs = h[4];
+    out->col_max_rel = h[5];
+    out->mass = h[6];
+  }
   s->packed_rows = false;
   return repack(s);
 }

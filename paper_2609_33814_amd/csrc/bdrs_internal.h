@@ -87,6 +87,22 @@ struct PartialRec {
   int pad;
 };
 
+// Partial of the barycentric sweep (same 24-byte slot as PartialRec): shift M,
+// shifted sum S and the shifted sum of the input points' coordinates V.
+struct PartialBary {
+  double M;
+  float S;
+  float V[3];
+};
+static_assert(sizeof(PartialBary) == sizeof(PartialRec), "bary partials reuse the partial slots");
+
+// What a sweep accumulates besides the shifted sum.
+enum SweepMode {
+  kSweepPlain = 0,
+  kSweepCert = 1,   // cost-weighted sum (Algorithm 2's N_j)
+  kSweepBary = 2    // coordinate-weighted sums (barycentric projection)
+};
+
 struct Partials {
   PartialRec* rec;  // [S][np]
   int splits;       // allocated splits
@@ -98,7 +114,9 @@ enum FinishKind {
   kFinishColCert = 2,   // column epilogue + Algorithm 2 column statistics
   kFinishLse = 3,       // plain LSE output (parity entry point)
   kFinishRepair = 4,    // repair deficits p_i
-  kFinishCertOnly = 5   // Algorithm 2 column statistics of the last finished iteration
+  kFinishCertOnly = 5,  // Algorithm 2 column statistics of the last finished iteration
+  kFinishPlanRow = 6,   // state plan: row sums and barycentric projection (bary partials)
+  kFinishPlanCol = 7    // state plan: column sums
 };
 
 struct LaunchCtx {
@@ -112,6 +130,10 @@ struct LaunchCtx {
   double* cert_part;   // [cert_blocks][8]
   double* cert_out;    // [kCertSlots]
   int cert_blocks;
+  double* plan_row;    // [rows.np] row sums of the state plan (tile order)
+  double* plan_col;    // [cols.np] column sums of the state plan (tile order)
+  double* plan_stats;  // [kCertSlots] marginal-error statistics
+  double origin[3];    // common origin of the stored coordinates
 };
 
 // One work item of a batched phase: problem index into the descriptor array,
@@ -130,6 +152,11 @@ hipError_t launch_advance(Ctrl* ctrl, int n, hipStream_t s);
 hipError_t launch_prologue(const LaunchCtx& c);                       // lt and A_C for iteration k
 hipError_t launch_pack(const LaunchCtx& c, bool transpose, const double* w, double eps);
 hipError_t launch_pack_rows_from_lah(const LaunchCtx& c, double eps);
+// state plan: input side packed from the state (columns: log beta, rows: log alpha)
+hipError_t launch_pack_state(const LaunchCtx& c, bool transpose, double eps);
+// row sweep accumulating the input coordinates (barycentric projection)
+hipError_t launch_sweep_bary(const LaunchCtx& c, int splits, double eps);
+hipError_t launch_plan_stats(const LaunchCtx& c);
 hipError_t launch_cert_reduce(const LaunchCtx& c);
 hipError_t launch_repair_pack(const LaunchCtx& c);
 hipError_t launch_repair_reduce(const LaunchCtx& c);

@@ -156,12 +156,14 @@ __device__ __forceinline__ Group<D> load_group(gfloat* __restrict__ in_off, gflo
 // certificate, the cost-weighted sum).  The next tile's record and the next
 // group of points are requested before the current group is computed, so the
 // scalar loads overlap the arithmetic.
-template <int D, bool CERT>
+template <int D, int MODE>
 __device__ __forceinline__ void sweep_block(
     gfloat* __restrict__ out_abs, int np_out,
     gfloat* __restrict__ in_off, gfloat* __restrict__ in_A, gtile* __restrict__ in_tile,
     int ntiles_in, int count_in, int tps, const int* __restrict__ hint,
     PartialRec* __restrict__ part, gctrl* __restrict__ ctrl, double eps_arg, int kofs, int bx, int split) {
+  constexpr bool CERT = MODE == kSweepCert;
+  constexpr bool BARY = MODE == kSweepBary;
   const int p = bx * kSweepBlock + threadIdx.x;
   const int t0 = split * tps;
   const int t1 = min(t0 + tps, ntiles_in);
@@ -202,8 +204,18 @@ __device__ __forceinline__ void sweep_block(
     }
   }
   float S = 0.0f, N = 0.0f;
+  float V[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) V[d] = 0.0f;
   if (t0 >= t1) {
-    part[(size_t)split * np_out + p] = PartialRec{M, S, N, J, 0};
+    if (BARY) {
+      PartialBary* pb = reinterpret_cast<PartialBary*>(part) + (size_t)split * np_out + p;
+      pb->M = M;
+      pb->S = S;
+      for (int d = 0; d < 3; ++d) pb->V[d] = 0.0f;
+    } else {
+      part[(size_t)split * np_out + p] = PartialRec{M, S, N, J, 0};
+    }
     return;
   }
 
@@ -259,6 +271,10 @@ __device__ __forceinline__ void sweep_block(
         const float sc = fast_exp2((float)(M - tmd));
         S *= sc;
         if (CERT) N *= sc;
+        if (BARY) {
+#pragma unroll
+          for (int d = 0; d < D; ++d) V[d] *= sc;
+        }
         M = tmd;
         J = t * kTile + qi;
       }
@@ -267,6 +283,9 @@ __device__ __forceinline__ void sweep_block(
     const TileVals<D> nxt = load_tile<D>(in_tile + tn);
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
     float n0 = 0.f, n1 = 0.f;
+    float vt[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) vt[d] = 0.0f;
 #pragma unroll
     for (int g = 0; g < kTile / kGroup; ++g) {
       // request the next group (the first group of the next tile after the last)
@@ -293,12 +312,29 @@ __device__ __forceinline__ void sweep_block(
           }
           if (u & 1) n1 = fmaf(c2, e, n1); else n0 = fmaf(c2, e, n0);
         }
+        if (BARY) {
+#pragma unroll
+          for (int d = 0; d < D; ++d) vt[d] = fmaf(e, grp.b[d][u], vt[d]);
+        }
       }
       grp = nx;
     }
-    S += (s0 + s1) + (s2 + s3);
+    const float st = (s0 + s1) + (s2 + s3);
+    S += st;
     if (CERT) N += n0 + n1;
+    if (BARY) {
+      // sum_q e_q y_q = c_t sum_q e_q + sum_q e_q b_q (points = tile centre + offset)
+#pragma unroll
+      for (int d = 0; d < D; ++d) V[d] += fmaf(cur.ctr[d], st, vt[d]);
+    }
     cur = nxt;
+  }
+  if (BARY) {
+    PartialBary* pb = reinterpret_cast<PartialBary*>(part) + (size_t)split * np_out + p;
+    pb->M = M;
+    pb->S = S;
+    for (int d = 0; d < 3; ++d) pb->V[d] = d < D ? V[d] : 0.0f;
+    return;
   }
   PartialRec rec;
   rec.M = M;
@@ -309,20 +345,20 @@ __device__ __forceinline__ void sweep_block(
   part[(size_t)split * np_out + p] = rec;
 }
 
-template <int D, bool CERT>
+template <int D, int MODE>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(
     const float* __restrict__ out_abs, int np_out,
     const float* __restrict__ in_off, const float* __restrict__ in_A, const TileRec* __restrict__ in_tile,
     int ntiles_in, int count_in, int tps, const int* __restrict__ hint,
     PartialRec* __restrict__ part, const Ctrl* __restrict__ ctrl, double eps_arg, int kofs) {
-  sweep_block<D, CERT>((gfloat*)out_abs, np_out, (gfloat*)in_off, (gfloat*)in_A, (gtile*)in_tile, ntiles_in,
+  sweep_block<D, MODE>((gfloat*)out_abs, np_out, (gfloat*)in_off, (gfloat*)in_A, (gtile*)in_tile, ntiles_in,
                        count_in, tps, hint, part, (gctrl*)ctrl, eps_arg, kofs, blockIdx.x, blockIdx.y);
 }
 
 // Batched sweep: block i runs work item i = (problem, block of outputs, split)
 // of a list over several problems; the arithmetic per item is the same as in
 // the single-problem launch.
-template <int D, bool CERT>
+template <int D, int MODE>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep_batch(const BatchItem* __restrict__ items,
                                                         const LaunchCtx* __restrict__ descs, int transpose,
                                                         int kofs) {
@@ -332,7 +368,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep_batch(const BatchItem* __
   const SideDev& in = transpose ? c.rows : c.cols;
   const int splits = transpose ? c.splits_col : c.splits_row;
   const int tps = (in.ntiles + splits - 1) / splits;
-  sweep_block<D, CERT>((gfloat*)out.abs, out.np, (gfloat*)in.off, (gfloat*)in.A, (gtile*)in.tile, in.ntiles,
+  sweep_block<D, MODE>((gfloat*)out.abs, out.np, (gfloat*)in.off, (gfloat*)in.A, (gtile*)in.tile, in.ntiles,
                        in.count, tps, out.hint, c.part.rec, (gctrl*)c.ctrl, -1.0, kofs, it.blk, it.split);
 }
 
@@ -490,6 +526,32 @@ __device__ __forceinline__ void pack_weight(const SideDev& sd, int dim, int p, d
   else pack_weight_d<3>(sd, p, w, kap2);
 }
 
+// Merge of the barycentric partials of output p: shift, shifted sum and the
+// shifted coordinate sums, in float64.
+struct MergedBary {
+  double lse;   // natural-log LSE
+  double V[3];  // coordinate sums relative to the merged sum
+};
+
+__device__ __forceinline__ MergedBary merge_bary(const PartialRec* __restrict__ part, int splits, int np, int p) {
+  const PartialBary* pb = reinterpret_cast<const PartialBary*>(part);
+  double mx = -INFINITY;
+  for (int s = 0; s < splits; ++s) mx = fmax(mx, pb[(size_t)s * np + p].M);
+  MergedBary r;
+  double S = 0.0, V[3] = {0.0, 0.0, 0.0};
+  if (mx > -INFINITY) {
+    for (int s = 0; s < splits; ++s) {
+      const PartialBary q = pb[(size_t)s * np + p];
+      const double w = exp2(q.M - mx);
+      S += w * (double)q.S;
+      for (int d = 0; d < 3; ++d) V[d] += w * (double)q.V[d];
+    }
+  }
+  r.lse = kLn2D * (mx + log2(S));
+  for (int d = 0; d < 3; ++d) r.V[d] = S > 0.0 ? V[d] / S : 0.0;
+  return r;
+}
+
 // Merge + epilogue of one tile (bx) of 64 outputs; nblocks = tiles of the
 // output side (the column epilogue's last block advances k).
 __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, int kind, int splits,
@@ -498,16 +560,35 @@ __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, 
   const int p = bx * kTile + threadIdx.x;
   const int np = out.np;
   if (p >= np) return;
+  const bool real = p < out.count;
+  if (kind == kFinishPlanRow) {
+    // state plan: (X 1)_i = alpha_i sum_j K_ij beta_j, barycentre sum_j X_ij y_j / (X 1)_i
+    const MergedBary mb = merge_bary(c.part.rec, splits, np, p);
+    if (real) {
+      c.plan_row[p] = exp(c.st.la[p] + mb.lse);
+      if (lse_out) {
+        const int i = out.perm[p];
+        for (int d = 0; d < c.dim; ++d) lse_out[(size_t)i * c.dim + d] = c.origin[d] + mb.V[d];
+      }
+    }
+    return;
+  }
   const bool cert = (kind == kFinishColCert || kind == kFinishCertOnly);
   const Merged mg = merge_splits(c.part.rec, splits, np, p);
-  const bool real = p < out.count;
-  if (real && mg.J >= 0) out.hint[p] = mg.J;
+  // the warm start of the next sweep of this side: only the iteration's own sweeps set it
+  const bool iter_kind = kind == kFinishRow || kind == kFinishCol || kind == kFinishColCert;
+  if (real && iter_kind && mg.J >= 0) out.hint[p] = mg.J;
   const Ctrl* ctrl = c.ctrl;
   const long long k = ctrl->k + kofs;  // this iteration: the block's first plus the offset
   const double lam = ctrl->lam;
 
   if (kind == kFinishLse) {
     if (real) lse_out[out.perm[p]] = mg.lse;
+    return;
+  }
+  if (kind == kFinishPlanCol) {
+    // (X^T 1)_j = beta_j sum_i K_ij alpha_i
+    if (real) c.plan_col[p] = exp(c.st.lb1[p] + mg.lse);
     return;
   }
   if (kind == kFinishCertOnly) {
@@ -620,6 +701,71 @@ __global__ __launch_bounds__(kBlock) void k_pack_rows(LaunchCtx c, double eps) {
   if (p >= c.rows.np) return;
   const double kap2 = kLog2eD * c.ctrl->scale / eps;
   pack_weight(c.rows, c.dim, p, p < c.rows.count ? c.st.lah[p] : 0.0, kap2);
+}
+
+// State-plan weights of the input side: log beta^{k-1} on the columns (row sums
+// and barycentres), log alpha^{k-1} on the rows (column sums), at temperature eps.
+__global__ __launch_bounds__(kBlock) void k_pack_state(LaunchCtx c, int transpose, double eps) {
+  const SideDev& in = transpose ? c.rows : c.cols;
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= in.np) return;
+  const double kap2 = kLog2eD * c.ctrl->scale / eps;
+  const double* w = transpose ? c.st.la : c.st.lb1;
+  pack_weight(in, c.dim, p, p < in.count ? w[p] : 0.0, kap2);
+}
+
+// Marginal-error statistics of the state plan (float64): per block partial
+// sums / maxima over both sides, then one block combines them in order.
+// Partial layout per block: row l1, row max abs, row max rel, col l1, col max
+// abs, col max rel, total mass, pad.
+__global__ __launch_bounds__(kBlock) void k_plan_partial(LaunchCtx c) {
+  __shared__ double sh[kBlock / kTile][8];
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int stride = gridDim.x * kBlock;
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < c.rows.count; p += stride) {
+    const double r = c.rows.marg[p], x = c.plan_row[p];
+    const double e = fabs(x - r);
+    v[0] += e;
+    v[1] = fmax(v[1], e);
+    v[2] = fmax(v[2], e / r);
+    v[6] += x;
+  }
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < c.cols.count; p += stride) {
+    const double cj = c.cols.marg[p];
+    const double e = fabs(c.plan_col[p] - cj);
+    v[3] += e;
+    v[4] = fmax(v[4], e);
+    v[5] = fmax(v[5], e / cj);
+  }
+  v[0] = wave_sum(v[0]);
+  v[3] = wave_sum(v[3]);
+  v[6] = wave_sum(v[6]);
+  v[1] = wave_max(v[1]);
+  v[2] = wave_max(v[2]);
+  v[4] = wave_max(v[4]);
+  v[5] = wave_max(v[5]);
+  const int wv = threadIdx.x / kTile;
+  if ((threadIdx.x & (kTile - 1)) == 0)
+    for (int i = 0; i < 8; ++i) sh[wv][i] = v[i];
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const int i = threadIdx.x;
+    double a = sh[0][i];
+    for (int w = 1; w < kBlock / kTile; ++w) a = (i == 0 || i == 3 || i == 6) ? a + sh[w][i] : fmax(a, sh[w][i]);
+    c.cert_part[(size_t)blockIdx.x * 8 + i] = a;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_plan_final(LaunchCtx c, int nblocks) {
+  if (threadIdx.x < 8) {
+    const int i = threadIdx.x;
+    double a = c.cert_part[i];
+    for (int b = 1; b < nblocks; ++b) {
+      const double x = c.cert_part[(size_t)b * 8 + i];
+      a = (i == 0 || i == 3 || i == 6) ? a + x : fmax(a, x);
+    }
+    c.plan_stats[i] = a;
+  }
 }
 
 // Repair weights: log t_j + log(1 - e_j), e_j = min(1, c_j / s_j) (-inf where e_j = 1).
@@ -834,12 +980,12 @@ hipError_t launch_sweep_batch(const BatchItem* items, int nitems, const LaunchCt
   hipLaunchKernelGGL((k_sweep_batch<DD, CC>), dim3(nitems), dim3(kSweepBlock), 0, s, items, descs,   \
                      transpose ? 1 : 0, kofs)
   switch (dim * 2 + (cert ? 1 : 0)) {
-    case 2: BDRS_SWEEPB(1, false); break;
-    case 3: BDRS_SWEEPB(1, true); break;
-    case 4: BDRS_SWEEPB(2, false); break;
-    case 5: BDRS_SWEEPB(2, true); break;
-    case 6: BDRS_SWEEPB(3, false); break;
-    case 7: BDRS_SWEEPB(3, true); break;
+    case 2: BDRS_SWEEPB(1, kSweepPlain); break;
+    case 3: BDRS_SWEEPB(1, kSweepCert); break;
+    case 4: BDRS_SWEEPB(2, kSweepPlain); break;
+    case 5: BDRS_SWEEPB(2, kSweepCert); break;
+    case 6: BDRS_SWEEPB(3, kSweepPlain); break;
+    case 7: BDRS_SWEEPB(3, kSweepCert); break;
     default: return hipErrorInvalidValue;
   }
 #undef BDRS_SWEEPB
@@ -895,12 +1041,30 @@ hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int split
                      in.A, in.tile, in.ntiles, in.count, tps, out.hint,                                  \
                      c.part.rec, c.ctrl, eps_arg, kofs)
   switch (c.dim * 2 + (cert ? 1 : 0)) {
-    case 2: BDRS_SWEEP(1, false); break;
-    case 3: BDRS_SWEEP(1, true); break;
-    case 4: BDRS_SWEEP(2, false); break;
-    case 5: BDRS_SWEEP(2, true); break;
-    case 6: BDRS_SWEEP(3, false); break;
-    case 7: BDRS_SWEEP(3, true); break;
+    case 2: BDRS_SWEEP(1, kSweepPlain); break;
+    case 3: BDRS_SWEEP(1, kSweepCert); break;
+    case 4: BDRS_SWEEP(2, kSweepPlain); break;
+    case 5: BDRS_SWEEP(2, kSweepCert); break;
+    case 6: BDRS_SWEEP(3, kSweepPlain); break;
+    case 7: BDRS_SWEEP(3, kSweepCert); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef BDRS_SWEEP
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_bary(const LaunchCtx& c, int splits, double eps) {
+  const SideDev& out = c.rows;
+  const SideDev& in = c.cols;
+  const int tps = (in.ntiles + splits - 1) / splits;
+  dim3 grid(out.np / kSweepBlock, splits);
+#define BDRS_SWEEP(DD)                                                                                  \
+  hipLaunchKernelGGL((k_sweep<DD, kSweepBary>), grid, dim3(kSweepBlock), 0, c.stream, out.abs, out.np,   \
+                     in.off, in.A, in.tile, in.ntiles, in.count, tps, out.hint, c.part.rec, c.ctrl, eps, 0)
+  switch (c.dim) {
+    case 1: BDRS_SWEEP(1); break;
+    case 2: BDRS_SWEEP(2); break;
+    case 3: BDRS_SWEEP(3); break;
     default: return hipErrorInvalidValue;
   }
 #undef BDRS_SWEEP
@@ -929,6 +1093,19 @@ hipError_t launch_pack(const LaunchCtx& c, bool transpose, const double* w, doub
 
 hipError_t launch_pack_rows_from_lah(const LaunchCtx& c, double eps) {
   hipLaunchKernelGGL(k_pack_rows, dim3(c.rows.np / kBlock), dim3(kBlock), 0, c.stream, c, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_state(const LaunchCtx& c, bool transpose, double eps) {
+  const SideDev& in = transpose ? c.rows : c.cols;
+  hipLaunchKernelGGL(k_pack_state, dim3(in.np / kBlock), dim3(kBlock), 0, c.stream, c, transpose ? 1 : 0, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_stats(const LaunchCtx& c) {
+  // the certificate's partial buffer holds cert_blocks x 8 doubles
+  hipLaunchKernelGGL(k_plan_partial, dim3(c.cert_blocks), dim3(kBlock), 0, c.stream, c);
+  hipLaunchKernelGGL(k_plan_final, dim3(1), dim3(kBlock), 0, c.stream, c, c.cert_blocks);
   return hipGetLastError();
 }
 
