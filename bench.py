@@ -42,6 +42,16 @@ EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters
 TRAFFIC_KERNEL_SHA256 = "2a2900027faad2a8e829bb0f88fb312ec67ef234c10b706d8fa3bf0e01685190"
 TRAFFIC_SPLITS = 16
 TRAFFIC_BYTES_PER_LAUNCH = 9.62e6
+# Counters of the same profile (rocprofv3 --pmc, per dispatch of k_sweep<2,false>):
+# VALU lane instructions per entry (SQ_INSTS_VALU x 64 / entries), v_exp_f32 per
+# entry (SQ_INSTS_VALU_TRANS_F32 x 64 / entries), VALU issue utilisation
+# (lane instructions / duration / (256 x 64 x 2.4 GHz)) and rocprof's VALUBusy.
+PROFILE_COUNTERS = {"valu_instr_per_entry": 5.67, "exp_per_entry": 1.000, "valu_issue_frac": 0.738,
+                    "VALUBusy": 75.6, "source": "profiles/k_sweep_grid128x128.md"}
+
+
+def profiled_counters(splits_row: int):
+    return PROFILE_COUNTERS if measured_traffic(splits_row) is not None else None
 
 
 def measured_traffic(splits_row: int):
@@ -466,7 +476,9 @@ def main() -> int:
                      "unit": "Gentries/s", "frac": round(achieved / peak, 4),
                      "traffic": measured_traffic(splits_row), "traffic_unit": "HBM bytes per launch",
                      "kernel": "k_sweep<2,false>", "per_launch_us": round(per_sweep_ms * 1e3, 3),
-                     "splits": splits_row},
+                     "splits": splits_row,
+                     "exp_per_s": round(achieved * 1e9, 0),  # one v_exp_f32 per entry
+                     "counters": profiled_counters(splits_row)},
         "cpu_baseline": cpu,
         "time_to_1pct": ttg,
     }
