@@ -219,11 +219,19 @@ def serve_mode(args) -> int:
                 if delay > 0:
                     time.sleep(delay)
                 tickets[q] = srv.submit(probs[q], eta=ETA, tau=tau, max_iters=cap)
+                if (q + 1) % 16 == 0:
+                    print(f"[bench]   max_slots={max_slots}: {q + 1} submitted at "
+                          f"{time.perf_counter() - start:.1f} s", flush=True)
 
         th = threading.Thread(target=feeder)
         th.start()
         th.join()
-        res = [srv.wait(t) for t in tickets]
+        res = []
+        for q, t in enumerate(tickets):
+            res.append(srv.wait(t))
+            if (q + 1) % 16 == 0:
+                print(f"[bench]   max_slots={max_slots}: {q + 1} done at {time.perf_counter() - start:.1f} s",
+                      flush=True)
         srv.close()
         lat = np.array([r["t_done"] - r["t_submit"] for r in res])
         span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)

@@ -19,6 +19,22 @@ then, when requested, the certificate of Prop. 3 from (lah, lbh, lt, eps_k).
 
 The state also keeps log beta^{k-1}: the next extrapolation needs both
 beta^k and beta^{k-1}, and the tuple Algorithm 1 returns lacks it.
+
+Ablation variants (lambda = 1; the controlled ablation of the appendix and
+Cor. 1, which names the two changes that turn annealed Sinkhorn into Dual
+BDRS).  All share the column update at eps_k = eta / (k + 1), i.e. the
+kernel K^{.(k+1)}, the schedule and the initialisation; the row update is
+
+  log a^k = [theta_k log a^{k-1}] + log r - LSE_j(log t_j - C_ij / eps_row)
+
+with OLD_KERNEL: eps_row = eta / k (the kernel K^{.k}; K^{.0} is all ones,
+eps_row = inf) instead of eps_k; NO_MOMENTUM: t = b^{k-1} instead of the
+extrapolated b~^{k-1}; DEBIASED (with both of the former, the debiased
+annealed Sinkhorn): the bracketed factor with theta_k = 0 for k <= 1 and
+1 / k for k >= 2 (the first iteration that has a previous row scaling uses
+theta = 0, as the ablation's formula does for its first index).  The
+column update reads the row scaling a^k itself (for DEBIASED the factor
+included).
 """
 from __future__ import annotations
 
@@ -30,9 +46,24 @@ from .lse import implicit_lse
 from .certificate import certificate
 
 
+OLD_KERNEL, NO_MOMENTUM, DEBIASED = 1, 2, 4
+
+
 def schedule(eta: float, lam: float, k: int) -> float:
     """Effective temperature eta_k = eta / (lambda k + 1) (Algorithm 1)."""
     return eta / (lam * k + 1.0)
+
+
+def row_temperature(eta: float, lam: float, k: int, variant: int = 0) -> float:
+    """Temperature of the row update: eps_k, or for OLD_KERNEL that of K^{.k}."""
+    if variant & OLD_KERNEL:
+        return eta / k if k >= 1 else np.inf
+    return schedule(eta, lam, k)
+
+
+def debias_theta(k: int) -> float:
+    """theta_k of the debiased row update: 0 for k <= 1, 1 / k afterwards."""
+    return 0.0 if k <= 1 else 1.0 / k
 
 
 @dataclasses.dataclass
@@ -70,14 +101,25 @@ def col_update(prob, lah, eps):
     return np.log(prob.c) - implicit_lse(prob.y, prob.x, prob.cost_scale, eps, lah)
 
 
-def iterate(prob, st: State, eta: float, lam: float) -> State:
-    """One iteration of Algorithm 1; returns the new state (input untouched)."""
+def column_weights(st: "State", variant: int = 0):
+    """The row scaling the column update of the last iteration read."""
+    return st.la if variant & DEBIASED else st.lah
+
+
+def iterate(prob, st: State, eta: float, lam: float, variant: int = 0) -> State:
+    """One iteration of Algorithm 1 (or of an ablation variant); returns the new state."""
     k = st.k
     eps = schedule(eta, lam, k)
-    lt = momentum(st.lb1, st.lb2, lam)
-    lah = row_update(prob, lt, eps)
-    la = (1.0 - lam) * st.la + lam * lah
-    lbh = col_update(prob, lah, eps)
+    eps_row = row_temperature(eta, lam, k, variant)
+    lt = st.lb1.copy() if variant & NO_MOMENTUM else momentum(st.lb1, st.lb2, lam)
+    lah = row_update(prob, lt, eps_row)
+    if variant & DEBIASED:
+        la = debias_theta(k) * st.la + lah
+        colw = la
+    else:
+        la = (1.0 - lam) * st.la + lam * lah
+        colw = lah
+    lbh = col_update(prob, colw, eps)
     lb = (1.0 - lam) * st.lb1 + lam * lbh
     return State(la=la, lb1=lb, lb2=st.lb1.copy(), lah=lah, lbh=lbh, lt=lt, k=k + 1)
 
@@ -89,27 +131,38 @@ def cert_due(k: int, cert_every: int, last: int) -> bool:
 
 def run(prob, eta: float, lam: float, iters: int, cert_every: int = 0,
         omega: float = 1.0, tau_rel: float | None = None, state: State | None = None,
-        keep_states: bool = False):
+        keep_states: bool = False, variant: int = 0):
     """Run Algorithm 1 for up to ``iters`` iterations.
 
     Returns (state, certs, states): certs is a list of dicts (iteration k, the
     Prop. 3 quantities, and best-so-far bounds U_best = min U, L_best = max L);
     with ``tau_rel`` the loop stops at the first certificate whose best
     relative gap (U_best - L_best) / U_best is at most tau_rel.
+
+    For an ablation variant the certificate's plan Z uses the row update's
+    temperature and weights t, and its lower bound the column update's
+    temperature and row scaling (see ``certificate``).
     """
+    if variant and lam != 1.0:
+        raise ValueError("the ablation variants are defined for lambda = 1")
     st = State.initial(prob.m, prob.n) if state is None else state.copy()
     certs, states = [], []
     U_best, L_best = np.inf, -np.inf
     k_end = st.k + iters - 1
     for _ in range(iters):
         k = st.k
-        st = iterate(prob, st, eta, lam)
+        st = iterate(prob, st, eta, lam, variant)
         if keep_states:
             states.append(st.copy())
         if cert_due(k, cert_every, k_end):
             eps = schedule(eta, lam, k)
-            ce = certificate(prob.x, prob.y, prob.cost_scale, prob.r, prob.c,
-                             st.lah, st.lbh, st.lt, eps, omega)
+            if variant:
+                ce = certificate(prob.x, prob.y, prob.cost_scale, prob.r, prob.c,
+                                 st.lah, st.lbh, st.lt, row_temperature(eta, lam, k, variant), omega,
+                                 colw=column_weights(st, variant), eps_col=eps)
+            else:
+                ce = certificate(prob.x, prob.y, prob.cost_scale, prob.r, prob.c,
+                                 st.lah, st.lbh, st.lt, eps, omega)
             U_best = min(U_best, ce["U"])
             L_best = max(L_best, ce["L"])
             ce.update(k=k, U_best=U_best, L_best=L_best,

@@ -13,6 +13,15 @@ beta-tilde^{k-1}, eps = eta / (lambda k + 1), all in natural-log form here.
   mu_j = N_j / D_j, d_j = M_j + log D_j, s_j = exp(log t_j + d_j)
 * delta = 1/2 ||s - c||_1, U = sum_j s_j mu_j + Omega delta (Algorithm 2)
 * relative gap (U - L) / U (experiments, "relative duality gap").
+
+The upper bound only needs a plan Z = diag(A) K_eps diag(t) whose row sums
+are r, i.e. A = r / (K_eps t) (the proof of Prop. 3 uses nothing else), and
+the lower bound only a dual feasible pair: g is the soft c-transform of f at
+the temperature of the column update.  The ablation variants, whose row and
+column updates use different temperatures (or whose column update reads a
+debiased row scaling), therefore take U from the row update (A, t, eps) and
+L from the column update (its row scaling ``colw`` and temperature
+``eps_col``); for Algorithm 1 both coincide.
 """
 from __future__ import annotations
 
@@ -53,9 +62,9 @@ def lower_bound(r, c, lah, lbh, eps):
     return float(np.dot(r, f) + np.dot(c, g)), f, g
 
 
-def certificate(x, y, s, r, c, lah, lbh, lt, eps, omega=1.0):
+def certificate(x, y, s, r, c, lah, lbh, lt, eps, omega=1.0, colw=None, eps_col=None):
     """All quantities of Proposition 3 / Algorithm 2 for one iteration."""
-    L, f, g = lower_bound(r, c, lah, lbh, eps)
+    L, f, g = lower_bound(r, c, lah if colw is None else colw, lbh, eps if eps_col is None else eps_col)
     M, D, N = column_statistics(x, y, s, eps, lah)
     mu = N / D
     d = M + np.log(D)

@@ -11,6 +11,10 @@ recursion of ``alg1`` from outside it:
 * ``ipot``          -- IPOT of Xie et al. (2020, Algorithm 1) with L inner
   Sinkhorn steps on Q = G . Gamma, warm-started b, Gamma^1 = 1, b = 1/n;
   with L = 1 it coincides with BDRS (App. B mapping mu, nu, G, Gamma <-> r, c, K, X).
+* ``annealed_scalings`` -- the scaling recursions of the momentum / kernel
+  ablation (Cor. 1 and the ablation appendix) in the linear domain:
+  a^k = [(a^{k-1})^theta_k] r / (K^{.k or .(k+1)} t), t = b^{k-1} or
+  (b^{k-1})^2 / b^{k-2}, and the shared column update b^k = c / (K^{.(k+1)})^T a^k.
 """
 from __future__ import annotations
 
@@ -66,3 +70,29 @@ def ipot(C, mu, nu, beta, outer, inner=1):
         Gamma = a[:, None] * Q * b[None, :]
         out.append(Gamma)
     return out
+
+
+def annealed_scalings(C, r, c, eta, iters, old_kernel, momentum, debiased):
+    """Row / column scalings a^k, b^k (k = 0..iters-1) of the ablation family.
+
+    b^{-1} = b^{-2} = 1 and a^{-1} = 1; K^{.j} = exp(-j C / eta) (K^{.0} = 1);
+    theta_k = 0 for k <= 1 and 1 / k afterwards (debiased row update).
+    """
+    m, n = C.shape
+    a_prev = np.ones(m)
+    b1 = np.ones(n)
+    b2 = np.ones(n)
+    As, Bs = [], []
+    for k in range(iters):
+        Kr = np.exp(-(k if old_kernel else k + 1) * C / eta)
+        t = b1 * b1 / b2 if momentum else b1
+        a = r / (Kr @ t)
+        if debiased:
+            theta = 0.0 if k <= 1 else 1.0 / k
+            a = a_prev ** theta * a
+        Kc = np.exp(-(k + 1) * C / eta)
+        b = c / (Kc.T @ a)
+        As.append(a)
+        Bs.append(b)
+        a_prev, b2, b1 = a, b1, b
+    return As, Bs

@@ -361,3 +361,66 @@ def test_marginal_stats_by_hand():
     assert st["row_max_rel"] == pytest.approx(0.2)
     assert st["col_l1"] == pytest.approx(0.5) and st["col_max_abs"] == pytest.approx(0.25)
     assert st["col_max_rel"] == pytest.approx(1.0) and st["mass"] == pytest.approx(1.0)
+
+
+# ----------------------------------------------------------------------------
+# Momentum / kernel ablation family (Cor. 1, ablation appendix)
+# ----------------------------------------------------------------------------
+VARIANTS = {
+    "annealed_sinkhorn": alg1.OLD_KERNEL | alg1.NO_MOMENTUM,
+    "as_momentum": alg1.OLD_KERNEL,
+    "as_current_kernel": alg1.NO_MOMENTUM,
+    "debiased_as": alg1.OLD_KERNEL | alg1.NO_MOMENTUM | alg1.DEBIASED,
+    "dual_bdrs": 0,
+}
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_ablation_variants_equal_linear_domain_scalings(name):
+    v = VARIANTS[name]
+    p = small_problem(8, 11, 3, 31)
+    eta, iters = 1.0, 40
+    C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+    A, B = primal.annealed_scalings(C, p.r, p.c, eta, iters, bool(v & alg1.OLD_KERNEL),
+                                    not v & alg1.NO_MOMENTUM, bool(v & alg1.DEBIASED))
+    _, _, states = alg1.run(p, eta, 1.0, iters, keep_states=True, variant=v)
+    for k, st in enumerate(states):
+        assert np.allclose(st.la, np.log(A[k]), rtol=1e-10, atol=1e-10), (name, k)
+        assert np.allclose(st.lb1, np.log(B[k]), rtol=1e-10, atol=1e-10), (name, k)
+    if v == 0:   # the corner of the design with both changes is Dual BDRS itself
+        _, _, ref = alg1.run(p, eta, 1.0, iters, keep_states=True)
+        assert all(np.array_equal(a.la, b.la) and np.array_equal(a.lb1, b.lb1) for a, b in zip(states, ref))
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_ablation_plans_are_normalised(name):
+    """Every variant: the completed matrix diag(a^k) K^{.(k+1)} diag(b^k) has
+    column sums c, and the certificate's plan diag(A) K_row diag(t) row sums r."""
+    v = VARIANTS[name]
+    p = small_problem(9, 7, 2, 32)
+    eta = 0.7
+    C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+    _, _, states = alg1.run(p, eta, 1.0, 25, keep_states=True, variant=v)
+    for k in (0, 1, 2, 10, 24):
+        st = states[k]
+        X = np.exp(alg1.column_weights(st, v)[:, None] - (k + 1) * C / eta + st.lb1[None, :])
+        assert np.allclose(X.sum(axis=0), p.c, rtol=1e-11, atol=0), (name, k)
+        er = alg1.row_temperature(eta, 1.0, k, v)
+        Z = np.exp(st.lah[:, None] - C / er + st.lt[None, :])
+        assert np.allclose(Z.sum(axis=1), p.r, rtol=1e-11, atol=0), (name, k)
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_ablation_certificates_bracket_optimum(name):
+    v = VARIANTS[name]
+    for seed in (41, 42):
+        p = small_problem(7, 9, 2, seed)
+        C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+        pstar = lp.linprog_ot(C, p.r, p.c)
+        _, certs, _ = alg1.run(p, 0.5, 1.0, 120, cert_every=10, variant=v)
+        assert len(certs) == 12
+        for ce in certs:
+            assert ce["L"] <= pstar + 1e-12, (name, ce["k"])
+            assert pstar <= ce["U"] + 1e-12, (name, ce["k"])
+            # the certificate's plan Z has row sums r, hence total mass 1 (Prop. 3)
+            assert abs(ce["s"].sum() - 1.0) < 1e-10, (name, ce["k"])
