@@ -424,3 +424,5 @@ def test_ablation_certificates_bracket_optimum(name):
             assert pstar <= ce["U"] + 1e-12, (name, ce["k"])
             # the certificate's plan Z has row sums r, hence total mass 1 (Prop. 3)
             assert abs(ce["s"].sum() - 1.0) < 1e-10, (name, ce["k"])
+            # (f, g) is dual feasible: f_i + g_j <= C_ij (Prop. 3)
+            assert np.all(ce["f"][:, None] + ce["g"][None, :] <= C + 1e-12), (name, ce["k"])
