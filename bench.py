@@ -368,6 +368,42 @@ def colour10m_mode(args) -> int:
     return 0
 
 
+def ablation_mode(args) -> int:
+    """Momentum / kernel ablation on the 128x128 grids (seeds 21, 22), eta =
+    0.1, lambda = 1: every row-update variant run to a 1% certified relative
+    gap (cap 20000 iterations, certificate every 50)."""
+    import numpy as np
+    import torch
+    from paper_2609_33814_amd import bdrs, inputs
+    dev = torch.device("cuda:0")
+    prob = inputs.c2_problem()
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    X, Y, R, C = t(prob.x, torch.float32), t(prob.y, torch.float32), t(prob.r, torch.float64), t(prob.c, torch.float64)
+    cap = args.ttg_cap
+    out = {}
+    for name in bdrs.VARIANTS:
+        sv = bdrs.Solver(X, Y, R, C, prob.cost_scale, eta=ETA, variant=name)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ok, ce = sv.solve(0.01, cap, CERT_EVERY)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"reached": bool(ok), "iterations": int(ce["k"]) + 1, "seconds": round(dt, 4),
+                     "rel_gap_best": ce["rel_gap_best"], "U_best": ce["U_best"], "L_best": ce["L_best"]}
+        print(f"[bench] {name}: {out[name]}", flush=True)
+        sv.close()
+    line = {
+        "metric": "iterations and seconds to a 1% certified relative gap per row-update variant",
+        "value": out["dual_bdrs"]["seconds"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "grid128x128 Gaussian-mixture histograms (seeds 21, 22)", "eta": ETA,
+                   "lambda": 1.0, "cert_every": CERT_EVERY, "cap": cap},
+        "variants": out,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -377,11 +413,13 @@ def main() -> int:
     ap.add_argument("--no-ttg", action="store_true", help="skip the time-to-1%% runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--ttg-cap", type=int, default=20000)
-    ap.add_argument("--mode", choices=("sweep", "batch", "serve", "colour", "colour10m"), default="sweep",
+    ap.add_argument("--mode", choices=("sweep", "batch", "serve", "colour", "colour10m", "ablation"),
+                    default="sweep",
                     help="sweep: the headline line (default); batch: 64 uneven grid problems, "
                          "sequential solves vs one batched solve, to a 1%% gap; serve: Poisson "
                          "arrivals, FIFO one-at-a-time vs continuous batching; colour: 1M-point "
-                         "colour transfer; colour10m: 10M points, per-iteration time")
+                         "colour transfer; colour10m: 10M points, per-iteration time; ablation: "
+                         "row-update variants to a 1%% gap")
     ap.add_argument("--colour-iters", type=int, default=100)
     ap.add_argument("--serve-sides", default="32,64,128", help="grid sides of the serve requests")
     ap.add_argument("--requests", type=int, default=96)
@@ -414,6 +452,8 @@ def main() -> int:
         return colour_mode(args)
     if args.mode == "colour10m":
         return colour10m_mode(args)
+    if args.mode == "ablation":
+        return ablation_mode(args)
     prob = inputs.c2_problem()
     t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     X, Y = t(prob.x, torch.float32), t(prob.y, torch.float32)

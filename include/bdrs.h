@@ -52,6 +52,26 @@ typedef enum {
 
 /* flags */
 #define BDRS_F_REPAIR 1u     /* bdrs_certificate / bdrs_solve also compute <C, Z^> (repaired cost) */
+/* Ablation variants of the row update (Cor. 1 and the momentum / kernel
+ * ablation; lambda must be 1).  All keep the column update at eta / (k + 1)
+ * (kernel K^{.(k+1)}), the schedule and the initialisation:
+ *   BDRS_F_OLD_KERNEL   row update with the old kernel K^{.k} (temperature
+ *                       eta / k; K^{.0} is all ones) instead of K^{.(k+1)}
+ *   BDRS_F_NO_MOMENTUM  row update with t = b^{k-1} instead of the
+ *                       extrapolated b~^{k-1}
+ *   BDRS_F_DEBIASED     debiased annealed Sinkhorn: a^k = (a^{k-1})^theta_k r /
+ *                       (K^{.k} b^{k-1}), theta_k = 0 for k <= 1 and 1/k after;
+ *                       requires the two flags above
+ * Annealed Sinkhorn = OLD_KERNEL | NO_MOMENTUM, annealed Sinkhorn with
+ * momentum = OLD_KERNEL, current-kernel annealed Sinkhorn = NO_MOMENTUM,
+ * Dual BDRS = none.  The certificate stays valid: its plan Z uses the row
+ * update's temperature and weights t (so Z 1 = r) and its lower bound the
+ * column update's temperature and row scaling; with OLD_KERNEL or DEBIASED
+ * this takes one more column sweep per certificate, and such solvers are
+ * not accepted by bdrs_batch_solve. */
+#define BDRS_F_OLD_KERNEL 2u
+#define BDRS_F_NO_MOMENTUM 4u
+#define BDRS_F_DEBIASED 8u
 
 typedef struct bdrs_solver_* bdrs_solver;
 

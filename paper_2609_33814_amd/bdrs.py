@@ -19,6 +19,15 @@ TUNING_PATH = os.path.join(PKG, "tuning_gfx950.json")
 OK, NOT_CONVERGED = 0, 1
 E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_NUMERIC = -1, -2, -3, -4, -5
 F_REPAIR = 1
+F_OLD_KERNEL, F_NO_MOMENTUM, F_DEBIASED = 2, 4, 8
+# Row-update variants of the momentum / kernel ablation (lambda = 1).
+VARIANTS = {
+    "dual_bdrs": 0,
+    "annealed_sinkhorn": F_OLD_KERNEL | F_NO_MOMENTUM,
+    "as_momentum": F_OLD_KERNEL,
+    "as_current_kernel": F_NO_MOMENTUM,
+    "debiased_as": F_OLD_KERNEL | F_NO_MOMENTUM | F_DEBIASED,
+}
 
 EXPORTS = [
     "bdrs_workspace_size", "bdrs_create", "bdrs_step", "bdrs_certificate", "bdrs_solve",
@@ -201,7 +210,7 @@ class Solver:
     """
 
     def __init__(self, x, y, r, c, cost_scale, eta=1.0, lam=1.0, omega=1.0,
-                 stream=None, repair=False):
+                 stream=None, repair=False, variant: str = "dual_bdrs"):
         import torch
         self._torch = torch
         m, dim = int(x.shape[0]), int(x.shape[1])
@@ -218,7 +227,7 @@ class Solver:
         self.params = make_params(m, n, dim, _ptr(xx), _ptr(yy), _ptr(rr), _ptr(cc),
                                   float(cost_scale), float(eta), float(lam), float(omega),
                                   self._ws_ptr, self.bytes, int(self._stream.cuda_stream),
-                                  F_REPAIR if repair else 0)
+                                  (F_REPAIR if repair else 0) | VARIANTS[variant])
         h = ctypes.c_void_p()
         check(lib().bdrs_create(ctypes.byref(self.params), ctypes.byref(h)))
         self._h = h

@@ -134,7 +134,13 @@ bdrs_status check_params(const bdrs_params* p, size_t need) {
   if (!(std::isfinite(p->eta) && p->eta > 0)) return fail(BDRS_E_INVALID, "eta must be finite and > 0");
   if (!(p->lambda >= 1.0 && p->lambda < 2.0)) return fail(BDRS_E_INVALID, "lambda must lie in [1, 2)");
   if (!(std::isfinite(p->omega) && p->omega >= 0)) return fail(BDRS_E_INVALID, "omega must be finite and >= 0");
-  if (p->flags & ~BDRS_F_REPAIR) return fail(BDRS_E_INVALID, "unknown flags 0x%x", p->flags);
+  const uint32_t known = BDRS_F_REPAIR | BDRS_F_OLD_KERNEL | BDRS_F_NO_MOMENTUM | BDRS_F_DEBIASED;
+  if (p->flags & ~known) return fail(BDRS_E_INVALID, "unknown flags 0x%x", p->flags);
+  const uint32_t variant = p->flags & (BDRS_F_OLD_KERNEL | BDRS_F_NO_MOMENTUM | BDRS_F_DEBIASED);
+  if (variant && p->lambda != 1.0) return fail(BDRS_E_INVALID, "the ablation variant flags need lambda = 1");
+  if ((variant & BDRS_F_DEBIASED) && (variant & (BDRS_F_OLD_KERNEL | BDRS_F_NO_MOMENTUM)) !=
+                                         (BDRS_F_OLD_KERNEL | BDRS_F_NO_MOMENTUM))
+    return fail(BDRS_E_INVALID, "flags: BDRS_F_DEBIASED needs BDRS_F_OLD_KERNEL and BDRS_F_NO_MOMENTUM");
   if (!p->workspace) return fail(BDRS_E_INVALID, "workspace is NULL");
   if (((uintptr_t)p->workspace) % kAlign) return fail(BDRS_E_INVALID, "workspace must be 256-byte aligned");
   if (need == 0) need = make_layout(p->m, p->n, p->dim).total;
@@ -313,6 +319,15 @@ bdrs_status sync_k(bdrs_solver s) {
 
 double eps_at(const bdrs_solver s, long long k) { return s->prm.eta / (s->prm.lambda * (double)k + 1.0); }
 
+// temperature of the row update of iteration k (the certificate's plan uses it)
+double eps_row_at(const bdrs_solver s, long long k) {
+  if (s->prm.flags & BDRS_F_OLD_KERNEL) return k >= 1 ? s->prm.eta / (double)k : s->prm.eta * kFarTemperature;
+  return eps_at(s, k);
+}
+
+// variants whose certificate plan differs from the fused column statistics
+bool separate_cert(const bdrs_solver s) { return (s->prm.flags & (BDRS_F_OLD_KERNEL | BDRS_F_DEBIASED)) != 0; }
+
 bdrs_status hip_status(hipError_t e, const char* what) {
   if (e != hipSuccess) return fail(BDRS_E_DEVICE, "HIP error %s in %s", hipGetErrorString(e), what);
   return BDRS_OK;
@@ -361,7 +376,7 @@ bdrs_status repack(bdrs_solver s) {
   if ((e = launch_prologue(c)) != hipSuccess) return hip_status(e, "prologue");
   if (s->k > 0) {
     // rows.A <- log alpha-hat of iteration k-1 with that iteration's temperature
-    if ((e = launch_pack_rows_from_lah(c, eps_at(s, s->k - 1))) != hipSuccess) return hip_status(e, "repack");
+    if ((e = launch_pack_rows_from_lah(c, eps_row_at(s, s->k - 1))) != hipSuccess) return hip_status(e, "repack");
     s->packed_rows = true;
   }
   return BDRS_OK;
@@ -407,10 +422,26 @@ bdrs_status read_cert(bdrs_solver s, bool repair, bdrs_cert* out) {
   return cert_from_record(s, h, repair, out);
 }
 
+// Algorithm 2's column statistics of the last finished iteration by a separate
+// column sweep: the plan Z = diag(alpha-hat) K diag(t) at the row update's
+// temperature (rows re-packed from log alpha-hat when the last row epilogue
+// packed other weights or another temperature).
+bdrs_status enqueue_cert_only(bdrs_solver s) {
+  bdrs_status st;
+  if ((!s->packed_rows || separate_cert(s)) && (st = repack(s)) != BDRS_OK) return st;
+  const LaunchCtx& c = s->ctx;
+  const double eps = eps_row_at(s, s->k - 1);
+  hipError_t e;
+  if ((e = sweep(s, true, true, s->L.splits_col, eps)) != hipSuccess) return hip_status(e, "cert sweep");
+  if ((e = launch_finish(c, true, kFinishCertOnly, s->L.splits_col, eps, nullptr, 0)) != hipSuccess)
+    return hip_status(e, "cert finish");
+  return BDRS_OK;
+}
+
 bdrs_status enqueue_repair(bdrs_solver s) {
   const LaunchCtx& c = s->ctx;
   hipError_t e;
-  const double eps = eps_at(s, s->k - 1);
+  const double eps = eps_row_at(s, s->k - 1);
   if ((e = launch_repair_pack(c)) != hipSuccess) return hip_status(e, "repair pack");
   if ((e = sweep(s, false, false, s->L.splits_row, eps)) != hipSuccess) return hip_status(e, "repair sweep");
   if ((e = launch_finish(c, false, kFinishRepair, s->L.splits_row, eps, nullptr, 0)) != hipSuccess)
@@ -600,6 +631,8 @@ bdrs_status bdrs_batch_solve(const bdrs_solver* solvers, int32_t count, void* wo
       return fail(BDRS_E_STATE, "solvers[%d] is at iteration %lld, not a multiple of cert_every", i, solvers[i]->k);
     if (solvers[i]->prm.flags & BDRS_F_REPAIR)
       return fail(BDRS_E_INVALID, "solvers[%d]: BDRS_F_REPAIR is not supported in batches", i);
+    if (separate_cert(solvers[i]))
+      return fail(BDRS_E_INVALID, "solvers[%d]: old-kernel and debiased variants are not batched", i);
   }
   hipStream_t st_b = nullptr;
   HIPCHK(hipStreamCreateWithFlags(&st_b, hipStreamNonBlocking));
@@ -775,6 +808,7 @@ bdrs_status create_from_host(const bdrs_params* p, const float* px, const float*
   hc0.lam = p->lambda;
   hc0.scale = p->cost_scale;
   hc0.omega = p->omega;
+  hc0.variant = p->flags & (BDRS_F_OLD_KERNEL | BDRS_F_NO_MOMENTUM | BDRS_F_DEBIASED);
   chk(up(c.ctrl, &hc0, sizeof hc0));
   // Algorithm 1 initialisation: log alpha^{-1} = log beta^{-1} = log beta^{-2} = 0
   chk(hipMemsetAsync(c.st.la, 0, sizeof(double) * c.rows.np, stream));
@@ -819,13 +853,9 @@ bdrs_status bdrs_certificate(bdrs_solver s, bdrs_cert* out) {
   bdrs_status st = sync_k(s);
   if (st != BDRS_OK) return st;
   if (s->k < 1) return fail(BDRS_E_STATE, "no iteration has run yet");
-  if (!s->packed_rows && (st = repack(s)) != BDRS_OK) return st;
+  if ((st = enqueue_cert_only(s)) != BDRS_OK) return st;
   const LaunchCtx& c = s->ctx;
-  const double eps = eps_at(s, s->k - 1);
   hipError_t e;
-  if ((e = sweep(s, true, true, s->L.splits_col, eps)) != hipSuccess) return hip_status(e, "cert sweep");
-  if ((e = launch_finish(c, true, kFinishCertOnly, s->L.splits_col, eps, nullptr, 0)) != hipSuccess)
-    return hip_status(e, "cert finish");
   if ((e = launch_cert_reduce(c)) != hipSuccess) return hip_status(e, "cert reduce");
   const bool repair = (s->prm.flags & BDRS_F_REPAIR) != 0;
   if (repair && (st = enqueue_repair(s)) != BDRS_OK) return st;
@@ -847,7 +877,7 @@ bdrs_status bdrs_solve(bdrs_solver s, double tau, int32_t tau_relative, int32_t 
   for (int32_t i = 0; i < max_iters; ++i) {
     const long long k = s->k + pending;
     const bool due = ((k + 1) % cert_every == 0) || (i == max_iters - 1);
-    bdrs_status st = enqueue_iteration(s, due, pending);
+    bdrs_status st = enqueue_iteration(s, due && !separate_cert(s), pending);
     if (st != BDRS_OK) return st;
     ++pending;
     if (!due) continue;
@@ -855,6 +885,7 @@ bdrs_status bdrs_solve(bdrs_solver s, double tau, int32_t tau_relative, int32_t 
     if ((e = launch_advance(s->ctx.ctrl, pending, s->ctx.stream)) != hipSuccess) return hip_status(e, "advance");
     s->k += pending;
     pending = 0;
+    if (separate_cert(s) && (st = enqueue_cert_only(s)) != BDRS_OK) return st;
     if ((e = launch_cert_reduce(s->ctx)) != hipSuccess) return hip_status(e, "cert reduce");
     if (repair && (st = enqueue_repair(s)) != BDRS_OK) return st;
     st = read_cert(s, repair, &ce);

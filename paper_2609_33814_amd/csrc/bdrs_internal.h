@@ -24,9 +24,17 @@ constexpr int kCertSlots = 16;    // doubles in a certificate record
 
 // Device-resident control block of one solver: the iteration counter lives
 // here so that a captured block of iterations can be replayed at any k.
+// Variant bits of Ctrl::variant (the same values as the public flags).
+constexpr unsigned kVarOldKernel = 2u, kVarNoMomentum = 4u, kVarDebiased = 8u;
+// Temperature standing in for the all-ones kernel K^{.0} of the old-kernel row
+// update at k = 0: a factor 1e30 above eta makes every cost term vanish in
+// float32 and float64 alike.
+constexpr double kFarTemperature = 1e30;
+
 struct Ctrl {
   long long k;             // first iteration of the current block of Algorithm 1
-  unsigned int pad0, pad1;
+  unsigned int variant;    // ablation variant bits (0: Algorithm 1)
+  unsigned int pad1;
   double eta, lam, scale;  // eta, lambda, cost scale s
   double omega;
 };
@@ -145,6 +153,8 @@ struct BatchItem {
 // Kernel launchers (bdrs_kernels.hip).  Each returns the launch status.
 // kofs: offset of the iteration inside the current block (k = Ctrl::k + kofs);
 // launch_advance adds a finished block's length to Ctrl::k.
+// An iteration's sweeps (eps_arg <= 0) take the row update's temperature when
+// the rows are the outputs and the column update's otherwise.
 hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int splits, double eps_arg, int kofs);
 hipError_t launch_finish(const LaunchCtx& c, bool transpose, FinishKind kind, int splits,
                          double eps_arg, double* lse_out, int kofs);

@@ -50,6 +50,17 @@ __device__ __forceinline__ double eps_of(CtrlPtr c, double eps_arg, int kshift) 
   return c->eta / (c->lam * (double)(c->k + kshift) + 1.0);  // eta_k = eta / (lambda k + 1)
 }
 
+// Temperature of the row update: eta_k, or eta / k for the old kernel K^{.k}.
+template <typename CtrlPtr>
+__device__ __forceinline__ double eps_row_of(CtrlPtr c, double eps_arg, int kshift) {
+  if (eps_arg > 0.0) return eps_arg;
+  if (c->variant & kVarOldKernel) {
+    const long long k = c->k + kshift;
+    return k >= 1 ? c->eta / (double)k : c->eta * kFarTemperature;
+  }
+  return eps_of(c, -1.0, kshift);
+}
+
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // Wavefront all-reductions of a double with DPP lane moves inside each row of
@@ -161,13 +172,14 @@ __device__ __forceinline__ void sweep_block(
     gfloat* __restrict__ out_abs, int np_out,
     gfloat* __restrict__ in_off, gfloat* __restrict__ in_A, gtile* __restrict__ in_tile,
     int ntiles_in, int count_in, int tps, const int* __restrict__ hint,
-    PartialRec* __restrict__ part, gctrl* __restrict__ ctrl, double eps_arg, int kofs, int bx, int split) {
+    PartialRec* __restrict__ part, gctrl* __restrict__ ctrl, double eps_arg, int kofs, int bx, int split,
+    bool row_sweep) {
   constexpr bool CERT = MODE == kSweepCert;
   constexpr bool BARY = MODE == kSweepBary;
   const int p = bx * kSweepBlock + threadIdx.x;
   const int t0 = split * tps;
   const int t1 = min(t0 + tps, ntiles_in);
-  const double eps = eps_of(ctrl, eps_arg, kofs);
+  const double eps = row_sweep ? eps_row_of(ctrl, eps_arg, kofs) : eps_of(ctrl, eps_arg, kofs);
   const double kap2d = kLog2eD * ctrl->scale / eps;
   const float kap2x2 = (float)(2.0 * kap2d);
   const float kap2f = (float)kap2d;
@@ -350,9 +362,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(
     const float* __restrict__ out_abs, int np_out,
     const float* __restrict__ in_off, const float* __restrict__ in_A, const TileRec* __restrict__ in_tile,
     int ntiles_in, int count_in, int tps, const int* __restrict__ hint,
-    PartialRec* __restrict__ part, const Ctrl* __restrict__ ctrl, double eps_arg, int kofs) {
+    PartialRec* __restrict__ part, const Ctrl* __restrict__ ctrl, double eps_arg, int kofs, int row_sweep) {
   sweep_block<D, MODE>((gfloat*)out_abs, np_out, (gfloat*)in_off, (gfloat*)in_A, (gtile*)in_tile, ntiles_in,
-                       count_in, tps, hint, part, (gctrl*)ctrl, eps_arg, kofs, blockIdx.x, blockIdx.y);
+                       count_in, tps, hint, part, (gctrl*)ctrl, eps_arg, kofs, blockIdx.x, blockIdx.y,
+                       row_sweep != 0);
 }
 
 // Batched sweep: block i runs work item i = (problem, block of outputs, split)
@@ -369,7 +382,8 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep_batch(const BatchItem* __
   const int splits = transpose ? c.splits_col : c.splits_row;
   const int tps = (in.ntiles + splits - 1) / splits;
   sweep_block<D, MODE>((gfloat*)out.abs, out.np, (gfloat*)in.off, (gfloat*)in.A, (gtile*)in.tile, in.ntiles,
-                       in.count, tps, out.hint, c.part.rec, (gctrl*)c.ctrl, -1.0, kofs, it.blk, it.split);
+                       in.count, tps, out.hint, c.part.rec, (gctrl*)c.ctrl, -1.0, kofs, it.blk, it.split,
+                       transpose == 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -608,14 +622,23 @@ __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, 
     // Algorithm 1: log alpha-hat^k = log r - LSE, log alpha^k = (1-lambda) log alpha^{k-1} + lambda log alpha-hat^k
     const double eps = eps_of(ctrl, eps_arg, kofs);
     const double kap2 = kLog2eD * ctrl->scale / eps;
-    double lah = 0.0;
+    double colw = 0.0;
     if (real) {
-      lah = out.logmarg[p] - mg.lse;
+      const double lah = out.logmarg[p] - mg.lse;
       c.st.lah[p] = lah;
-      c.st.la[p] = (1.0 - lam) * c.st.la[p] + lam * lah;
+      if (ctrl->variant & kVarDebiased) {
+        // debiased row update: log a^k = theta_k log a^{k-1} + log r - LSE, theta_k = 0 (k <= 1), 1/k
+        const double theta = k <= 1 ? 0.0 : 1.0 / (double)k;
+        colw = theta * c.st.la[p] + lah;
+        c.st.la[p] = colw;
+      } else {
+        c.st.la[p] = (1.0 - lam) * c.st.la[p] + lam * lah;
+        colw = lah;
+      }
     }
-    // weights of the column sweep of the same iteration: w = log alpha-hat
-    pack_weight(c.rows, c.dim, p, lah, kap2);
+    // weights of the column sweep of the same iteration: log alpha-hat (the
+    // debiased variant: its row scaling a^k)
+    pack_weight(c.rows, c.dim, p, colw, kap2);
     return;
   }
   // column epilogue (plain or certificate)
@@ -633,9 +656,9 @@ __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, 
     c.st.lb2[p] = lb1;
     c.st.lb1[p] = lb;
     // momentum for iteration k+1: log beta-tilde^k = log beta^k + (log beta^k - log beta^{k-1}) / lambda
-    c.st.lt[nxt][p] = lb + (lb - lb1) / lam;
+    c.st.lt[nxt][p] = (ctrl->variant & kVarNoMomentum) ? lb : lb + (lb - lb1) / lam;
   }
-  const double eps1 = eps_of(ctrl, -1.0, kofs + 1);
+  const double eps1 = eps_row_of(ctrl, -1.0, kofs + 1);
   const double kap2n = kLog2eD * ctrl->scale / eps1;
   pack_weight(c.cols, c.dim, p, real ? c.st.lt[nxt][p] : 0.0, kap2n);
 
@@ -677,10 +700,10 @@ __global__ __launch_bounds__(kBlock) void k_prologue(LaunchCtx c) {
   double lt = 0.0;
   if (real) {
     const double lb1 = c.st.lb1[p], lb2 = c.st.lb2[p];
-    lt = lb1 + (lb1 - lb2) / lam;
+    lt = (c.ctrl->variant & kVarNoMomentum) ? lb1 : lb1 + (lb1 - lb2) / lam;
     c.st.lt[k & 1][p] = lt;
   }
-  const double kap2 = kLog2eD * c.ctrl->scale / eps_of(c.ctrl, -1.0, 0);
+  const double kap2 = kLog2eD * c.ctrl->scale / eps_row_of(c.ctrl, -1.0, 0);
   pack_weight(c.cols, c.dim, p, lt, kap2);
 }
 
@@ -779,7 +802,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_pack(LaunchCtx c) {
     const double cj = c.cols.marg[p];
     if (s > cj) w = c.st.lt[k & 1][p] + log1p(-cj / s);
   }
-  const double kap2 = kLog2eD * c.ctrl->scale / eps_of(c.ctrl, -1.0, -1);
+  const double kap2 = kLog2eD * c.ctrl->scale / eps_row_of(c.ctrl, -1.0, -1);
   pack_weight(c.cols, c.dim, p, w, kap2);
 }
 
@@ -807,8 +830,10 @@ __device__ void block_reduce_store(double* vals, int nv, double* dst) {
 __device__ __forceinline__ void cert_partial_block(const LaunchCtx& c, int bx, int nb) {
   double v[6] = {0, 0, 0, 0, 0, 0};
   const int stride = nb * kBlock;
+  const bool debiased = (c.ctrl->variant & kVarDebiased) != 0;
   for (int p = bx * kBlock + threadIdx.x; p < c.rows.count; p += stride) {
-    const double lah = c.st.lah[p];
+    // f = eps log A with A the row scaling the column update read (Prop. 3)
+    const double lah = debiased ? c.st.la[p] : c.st.lah[p];
     if (!isfinite(lah)) v[5] += 1.0;
     v[0] += c.rows.marg[p] * lah;
   }
@@ -1039,7 +1064,7 @@ hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int split
 #define BDRS_SWEEP(DD, CC)                                                                          \
   hipLaunchKernelGGL((k_sweep<DD, CC>), grid, dim3(kSweepBlock), 0, c.stream, out.abs, out.np, in.off,  \
                      in.A, in.tile, in.ntiles, in.count, tps, out.hint,                                  \
-                     c.part.rec, c.ctrl, eps_arg, kofs)
+                     c.part.rec, c.ctrl, eps_arg, kofs, transpose ? 0 : 1)
   switch (c.dim * 2 + (cert ? 1 : 0)) {
     case 2: BDRS_SWEEP(1, kSweepPlain); break;
     case 3: BDRS_SWEEP(1, kSweepCert); break;
@@ -1060,7 +1085,7 @@ hipError_t launch_sweep_bary(const LaunchCtx& c, int splits, double eps) {
   dim3 grid(out.np / kSweepBlock, splits);
 #define BDRS_SWEEP(DD)                                                                                  \
   hipLaunchKernelGGL((k_sweep<DD, kSweepBary>), grid, dim3(kSweepBlock), 0, c.stream, out.abs, out.np,   \
-                     in.off, in.A, in.tile, in.ntiles, in.count, tps, out.hint, c.part.rec, c.ctrl, eps, 0)
+                     in.off, in.A, in.tile, in.ntiles, in.count, tps, out.hint, c.part.rec, c.ctrl, eps, 0, 1)
   switch (c.dim) {
     case 1: BDRS_SWEEP(1); break;
     case 2: BDRS_SWEEP(2); break;

@@ -67,6 +67,8 @@ def _good(**kw):
     ("workspace", 0x10010, bdrs.E_INVALID, "aligned"),
     ("workspace_bytes", 100, bdrs.E_NOMEM, "workspace"),
     ("flags", 0x80, bdrs.E_INVALID, "flags"),
+    ("flags", 8, bdrs.E_INVALID, "DEBIASED"),
+    ("flags", 8 | 2, bdrs.E_INVALID, "DEBIASED"),
 ])
 def test_create_validates_before_any_device_call(field, value, code, word):
     p = _good(**{field: value})
@@ -217,3 +219,10 @@ def test_autotune_validates_on_host(saved_table):
     if not torch.cuda.is_available():
         assert L.bdrs_autotune(ctypes.byref(p), 5, ctypes.byref(e)) == bdrs.E_DEVICE
     assert bdrs.tune_table() == []
+
+
+def test_variant_flags_need_lambda_one():
+    p = _good(flags=2, lam=1.5)
+    h = ctypes.c_void_p()
+    assert bdrs.lib().bdrs_create(ctypes.byref(p), ctypes.byref(h)) == bdrs.E_INVALID
+    assert "lambda" in bdrs.last_error()
