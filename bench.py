@@ -28,6 +28,9 @@ sys.path.insert(0, ROOT)
 METRIC = "Gentries/s of fused LSE sweeps + time-to-1% rel. gap; p50/p99 serve latency"
 ETA = 0.1            # initial temperature of the grid workloads (chosen from the oracle's gap curves)
 CERT_EVERY = 50
+# Serving: requests above this many implicit entries per sweep (a 256x256 grid
+# problem has 4.3e9; the GPU is saturated well below that) run one at a time.
+BIG_WORK = 1e9
 CU, LANES, CLK = 256, 64, 2.4e9
 EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters show 6.78 VALU
                      # instructions per entry (one of them the exp) issued at 95% of the
@@ -183,7 +186,8 @@ def serve_mode(args) -> int:
     each stopped at a 1% relative gap.  The arrival rate is `load` times the
     sequential capacity measured on a sample.  The same arrival schedule is
     served twice: one request at a time (FIFO) and with continuous batching
-    (up to 32 running requests in a 1 GiB pool)."""
+    (up to 32 running requests in a 1 GiB pool, requests above BIG_WORK
+    entries per sweep one at a time)."""
     import threading
     import numpy as np
     import torch
@@ -208,8 +212,9 @@ def serve_mode(args) -> int:
     arrivals = np.cumsum(gaps) - gaps[0]
     print(f"[bench] sequential capacity {1 / mean_s:.2f} solves/s; arrival rate {rate:.2f}/s", flush=True)
 
-    def run(max_slots):
+    def run(max_slots, big_work=0.0):
         srv = bdrs.Server(pool, max_slots, block)
+        srv.set_policy(big_work)
         tickets = [None] * n_req
         start = time.perf_counter()
 
@@ -241,17 +246,23 @@ def serve_mode(args) -> int:
 
     fifo, res_f = run(1)
     print(f"[bench] FIFO one at a time: {fifo}", flush=True)
-    cont, res_c = run(32)
+    cont, res_c = run(32, BIG_WORK)
     print(f"[bench] continuous batching: {cont}", flush=True)
     same = all(a["cert"]["k"] == b["cert"]["k"] and a["cert"]["U"] == b["cert"]["U"] for a, b in zip(res_f, res_c))
+    plain = None
+    if args.serve_plain:
+        plain, _ = run(32, 0.0)
+        print(f"[bench] continuous batching, arrival-order admission: {plain}", flush=True)
     line = {
         "metric": "p50/p99 latency of OT solve requests to 1% relative gap (Poisson arrivals)",
         "value": cont["p99_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{n_req} grid requests, sides from {menu} (seed 52), arrivals Exp (seed 51) at "
                                f"{args.load} x sequential capacity", "eta": ETA, "lambda": 1.0,
-                   "block_iters": block, "pool_MiB": pool >> 20, "max_slots": 32},
+                   "block_iters": block, "pool_MiB": pool >> 20, "max_slots": 32,
+                   "big_work": BIG_WORK},
         "continuous_batching": cont, "fifo_sequential": fifo,
+        "continuous_batching_arrival_order": plain,
         "p99_speedup": round(fifo["p99_s"] / cont["p99_s"], 3),
         "results_equal_fifo_vs_batched": bool(same),
     }
@@ -422,6 +433,8 @@ def main() -> int:
                          "row-update variants to a 1%% gap")
     ap.add_argument("--colour-iters", type=int, default=100)
     ap.add_argument("--serve-sides", default="32,64,128", help="grid sides of the serve requests")
+    ap.add_argument("--serve-plain", action="store_true",
+                    help="also serve with arrival-order admission (no size-aware policy)")
     ap.add_argument("--requests", type=int, default=96)
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate / sequential capacity")
     ap.add_argument("--calib-copy", action="store_true",

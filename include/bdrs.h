@@ -313,6 +313,14 @@ BDRS_API bdrs_status bdrs_server_create(void *pool, size_t pool_bytes, int32_t m
 /* Validates and copies a request; thread-safe.  BDRS_E_NOMEM if its
  * workspace can never fit the pool.  *ticket identifies the request. */
 BDRS_API bdrs_status bdrs_server_submit(bdrs_server s, const bdrs_request *req, uint64_t *ticket);
+/* Admission policy (thread-safe; takes effect at the next block boundary).
+ * big_work > 0: a request with m n > big_work entries per sweep is admitted
+ * only while no other such request runs (large requests run one at a time,
+ * in arrival order), and smaller requests behind a waiting large one may be
+ * admitted before it; a GPU-saturating request then is not slowed down by
+ * other large ones, while small requests keep the benefit of batching.
+ * big_work <= 0 (the default): plain arrival-order admission. */
+BDRS_API bdrs_status bdrs_server_set_policy(bdrs_server s, double big_work);
 /* Non-blocking state of a request. */
 BDRS_API bdrs_status bdrs_server_poll(bdrs_server s, uint64_t ticket, bdrs_result *out);
 /* Blocks until the request is done (or the server stops). */

@@ -36,7 +36,7 @@ EXPORTS = [
     "bdrs_batch_solve", "bdrs_server_create", "bdrs_server_submit", "bdrs_server_poll",
     "bdrs_server_wait", "bdrs_server_stats", "bdrs_server_now", "bdrs_server_destroy",
     "bdrs_get_hints", "bdrs_set_hints", "bdrs_autotune_workspace_size", "bdrs_autotune",
-    "bdrs_tune_set", "bdrs_tune_get", "bdrs_tune_clear", "bdrs_plan",
+    "bdrs_tune_set", "bdrs_tune_get", "bdrs_tune_clear", "bdrs_plan", "bdrs_server_set_policy",
 ]
 
 
@@ -164,6 +164,7 @@ def lib() -> ctypes.CDLL:
         L.bdrs_tune_get.argtypes = [ctypes.c_int32, P(TuneEntry), P(ctypes.c_int32)]
         L.bdrs_tune_clear.argtypes = []
         L.bdrs_plan.argtypes = [vp, vp, vp, vp, P(PlanStats)]
+        L.bdrs_server_set_policy.argtypes = [vp, ctypes.c_double]
         L.bdrs_last_error.restype = ctypes.c_char_p
         L.bdrs_version.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -354,6 +355,10 @@ class Server:
         check(lib().bdrs_server_create(ptr, pool_bytes, int(max_slots), int(block_iters), ctypes.byref(h)))
         self._h = h
         self.block_iters = block_iters
+
+    def set_policy(self, big_work: float) -> None:
+        """Requests with m n > big_work run one at a time (<= 0: arrival order only)."""
+        check(lib().bdrs_server_set_policy(self._h, float(big_work)))
 
     def submit(self, prob, eta=1.0, lam=1.0, omega=1.0, tau=0.01, relative=True, max_iters=20000) -> int:
         """prob: an inputs.Problem (host arrays).  Returns the ticket."""

@@ -2,7 +2,9 @@
 //
 // A worker thread owns the GPU work.  Requests wait in a FIFO queue; at every
 // block boundary the worker admits requests from the head of the queue while
-// a slot is free and the pool can hold the request's workspace, runs one
+// a slot is free and the pool can hold the request's workspace (with the
+// size-aware policy, requests above a work threshold run one at a time, in
+// arrival order, and smaller ones may pass a waiting large one), runs one
 // block of iterations of all running requests through the batch engine,
 // reads every request's certificate, and retires the finished ones (their
 // pool memory is reused by the next admissions).  The per-request arithmetic
@@ -83,6 +85,7 @@ struct Request {
   int tau_relative = 1;
   int max_iters = 0;
   size_t bytes = 0, off = 0;
+  double work = 0;  // implicit entries per sweep, m n
   bdrs_solver solver = nullptr;
   int iters = 0;
   bdrs_result res{};
@@ -93,6 +96,7 @@ struct Request {
 struct bdrs_server_ {
   char* pool = nullptr;
   int max_slots = 1, block_iters = 50, device = 0;
+  double big_work = 0;  // > 0: requests with more entries per sweep run one at a time
   hipStream_t stream = nullptr;
   std::chrono::steady_clock::time_point t0;
   std::mutex mu;
@@ -146,13 +150,21 @@ void bdrs_server_::run() {
   std::vector<double> rec;
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    // admission at the block boundary: FIFO while a slot and memory are free
+    // admission at the block boundary: in arrival order while a slot and memory
+    // are free; with the size-aware policy a large request waits while another
+    // large one runs and the requests behind it that are small may pass it
     bool changed = false;
     while (!stop && !queue.empty() && (int)running.size() < max_slots) {
-      std::shared_ptr<Request> rq = queue.front();
+      bool big_running = false;
+      if (big_work > 0)
+        for (auto& r : running) big_running = big_running || r->work > big_work;
+      auto pick = queue.begin();
+      while (pick != queue.end() && big_work > 0 && big_running && (*pick)->work > big_work) ++pick;
+      if (pick == queue.end()) break;
+      std::shared_ptr<Request> rq = *pick;
       size_t off = 0;
-      if (!alloc->alloc(rq->bytes, &off)) break;  // head of line waits for memory
-      queue.pop_front();
+      if (!alloc->alloc(rq->bytes, &off)) break;  // the candidate waits for memory; nothing passes it
+      queue.erase(pick);
       rq->off = off;
       rq->prm.workspace = pool + off;
       rq->prm.workspace_bytes = rq->bytes;
@@ -302,6 +314,7 @@ bdrs_status bdrs_server_submit(bdrs_server sv, const bdrs_request* rq, uint64_t*
   auto r = std::make_shared<Request>();
   r->prm = p;
   r->bytes = make_layout(p.m, p.n, p.dim).total;
+  r->work = (double)p.m * (double)p.n;
   if (align_up(r->bytes) > sv->alloc->size())
     return fail(BDRS_E_NOMEM, "request needs %zu bytes, the pool holds %zu", r->bytes, sv->alloc->size());
   r->x.assign(rq->x, rq->x + (size_t)p.m * p.dim);
@@ -320,6 +333,15 @@ bdrs_status bdrs_server_submit(bdrs_server sv, const bdrs_request* rq, uint64_t*
   sv->all[r->ticket] = r;
   sv->queue.push_back(r);
   *ticket = r->ticket;
+  sv->cv_work.notify_all();
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_server_set_policy(bdrs_server sv, double big_work) {
+  if (!sv) return fail(BDRS_E_INVALID, "server is NULL");
+  if (!std::isfinite(big_work)) return fail(BDRS_E_INVALID, "big_work must be finite");
+  std::lock_guard<std::mutex> g(sv->mu);
+  sv->big_work = big_work > 0 ? big_work : 0.0;
   sv->cv_work.notify_all();
   return BDRS_OK;
 }

@@ -135,6 +135,7 @@ def test_server_calls_reject_null_server():
     assert L.bdrs_server_poll(None, 1, ctypes.byref(res)) == bdrs.E_INVALID
     assert L.bdrs_server_wait(None, 1, ctypes.byref(res)) == bdrs.E_INVALID
     assert L.bdrs_server_destroy(None) in (bdrs.OK, bdrs.E_INVALID)
+    assert L.bdrs_server_set_policy(None, 1e9) == bdrs.E_INVALID
 
 
 # ----------------------------------------------------------------------------

@@ -78,3 +78,38 @@ def test_server_rejects_and_isolates_bad_requests():
     srv.close()
     assert rb["status"] == bdrs.E_INVALID
     assert rg["status"] in (bdrs.OK, bdrs.NOT_CONVERGED) and rg["cert"]["k"] >= 49
+
+
+def test_size_aware_policy_runs_large_requests_one_at_a_time():
+    """With big_work set, two large requests never overlap and a small request
+    that arrived after the second large one is admitted before it; every
+    result still equals the request solved alone."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_33814_amd import bdrs
+    big1, big2 = inputs.grid_problem(24, 900, 901), inputs.grid_problem(24, 902, 903)  # 331776 entries
+    small = inputs.grid_problem(8, 904, 905)                                              # 4096 entries
+    eta, block = 0.3, 50
+    srv = bdrs.Server(pool_bytes=64 << 20, max_slots=8, block_iters=block)
+    srv.set_policy(1e5)
+    t1 = srv.submit(big1, eta=eta, tau=0.0, max_iters=300)
+    t2 = srv.submit(big2, eta=eta, tau=0.0, max_iters=300)
+    t3 = srv.submit(small, eta=eta, tau=0.0, max_iters=100)
+    r1, r2, r3 = srv.wait(t1), srv.wait(t2), srv.wait(t3)
+    srv.close()
+    assert r2["t_admit"] >= r1["t_done"]          # large requests do not overlap
+    assert r3["t_admit"] <= r2["t_admit"]         # the small one passed the waiting large one
+    for prob, r, cap in ((big1, r1, 300), (big2, r2, 300), (small, r3, 100)):
+        _, ce = alone(prob, eta, 0.0, cap, block)
+        assert r["cert"]["U"] == ce["U"] and r["cert"]["L"] == ce["L"] and r["cert"]["k"] == ce["k"]
+
+
+def test_set_policy_validates():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_33814_amd import bdrs
+    srv = bdrs.Server(pool_bytes=1 << 20, max_slots=1, block_iters=10)
+    with pytest.raises(bdrs.BdrsError):
+        srv.set_policy(float("inf"))
+    srv.set_policy(-1.0)   # back to arrival order
+    srv.close()
