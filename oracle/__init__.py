@@ -17,9 +17,11 @@ Modules (each function cites the passage of the paper it follows):
 * ``lp``           exact LP optima used to bracket the certificate
 * ``plan``         the state plan's marginals, marginal-error statistics and
                    barycentric projection (colour-transfer outputs)
+* ``rounding``     two-sided rounding of the state plan onto Pi(r, c) (the
+                   feasible-plan cost of the momentum / kernel ablation)
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test
 against something other than itself (identities of the paper, exact LP
 optima, closed forms, brute force).  No function is "parity unpinned".
 """
-from . import lse, alg1, certificate, repair, primal, lp, plan  # noqa: F401
+from . import lse, alg1, certificate, repair, primal, lp, plan, rounding  # noqa: F401

@@ -13,7 +13,7 @@ import mpmath
 import numpy as np
 import pytest
 
-from oracle import alg1, certificate, lp, lse, plan, primal, repair
+from oracle import alg1, certificate, lp, lse, plan, primal, repair, rounding
 from paper_2609_33814_amd import inputs
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -426,3 +426,66 @@ def test_ablation_certificates_bracket_optimum(name):
             assert abs(ce["s"].sum() - 1.0) < 1e-10, (name, ce["k"])
             # (f, g) is dual feasible: f_i + g_j <= C_ij (Prop. 3)
             assert np.all(ce["f"][:, None] + ce["g"][None, :] <= C + 1e-12), (name, ce["k"])
+
+
+# ----------------------------------------------------------------------------
+# Two-sided rounding of the state plan (Altschuler et al. 2017, Algorithm 2)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["dual_bdrs", "annealed_sinkhorn", "debiased_as"])
+def test_rounding_is_feasible_close_and_above_optimum(name):
+    v = VARIANTS[name]
+    p = small_problem(9, 12, 2, 51)
+    eta = 0.5
+    C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+    pstar = lp.linprog_ot(C, p.r, p.c)
+    for iters in (1, 5, 40):
+        st, _, _ = alg1.run(p, eta, 1.0, iters, variant=v)
+        eps = plan.plan_temperature(eta, 1.0, st.k)
+        F = np.exp(alg1.column_weights(st, v)[:, None] - C / eps + st.lb1[None, :])
+        d = rounding.dense_round(F, p.r, p.c)
+        G = d["G"]
+        assert np.all(G >= -1e-15)               # e_r, e_c >= 0 up to rounding (r - F'' 1 cancels)
+        assert np.allclose(G.sum(axis=1), p.r, rtol=1e-12, atol=1e-16)
+        assert np.allclose(G.sum(axis=0), p.c, rtol=1e-12, atol=1e-16)
+        # Lemma 7 of Altschuler et al.: ||G - F||_1 <= 2 (||F 1 - r||_1 + ||F^T 1 - c||_1)
+        bound = 2 * (np.abs(F.sum(axis=1) - p.r).sum() + np.abs(F.sum(axis=0) - p.c).sum())
+        assert np.abs(G - F).sum() <= bound * (1 + 1e-12) + 1e-15
+        cost = float((C * G).sum())
+        assert cost >= pstar - 1e-12
+        imp = rounding.implicit_round(p.x, p.y, p.cost_scale, eps, alg1.column_weights(st, v), st.lb1, p.r, p.c)
+        assert abs(imp["cost"] - cost) <= 1e-12 * max(1.0, cost)
+        assert abs(imp["mass"] - d["mass"]) <= 1e-14
+
+
+def test_rounding_leaves_feasible_plans_unchanged():
+    rng = np.random.default_rng(5)
+    r = rng.uniform(0.5, 1.5, 6); r /= r.sum()
+    c = rng.uniform(0.5, 1.5, 8); c /= c.sum()
+    G0 = np.outer(r, c)                      # feasible and positive
+    d = rounding.dense_round(G0, r, c)
+    assert np.allclose(d["G"], G0, rtol=1e-14, atol=0) and d["mass"] < 1e-15
+
+
+@pytest.mark.parametrize("lam", [1.5, 1.99])
+def test_rounding_of_obdrs_plans_scales_columns(lam):
+    """O-BDRS state plans miss both marginals, so both scaling steps act; the
+    implicit rounding equals the dense one and stays above the optimum."""
+    p = small_problem(10, 13, 3, 52)
+    eta = 0.6
+    C = lse.cost_matrix(p.x, p.y, p.cost_scale)
+    pstar = lp.linprog_ot(C, p.r, p.c)
+    scaled = 0
+    for iters in (2, 3, 10, 25):
+        st, _, _ = alg1.run(p, eta, lam, iters)
+        eps = plan.plan_temperature(eta, lam, st.k)
+        F = np.exp(st.la[:, None] - C / eps + st.lb1[None, :])
+        d = rounding.dense_round(F, p.r, p.c)
+        scaled += int(np.sum(d["y"] < 1.0 - 1e-9))
+        assert np.allclose(d["G"].sum(axis=0), p.c, rtol=1e-12, atol=1e-16)
+        assert np.allclose(d["G"].sum(axis=1), p.r, rtol=1e-12, atol=1e-16)
+        imp = rounding.implicit_round(p.x, p.y, p.cost_scale, eps, st.la, st.lb1, p.r, p.c)
+        cost = float((C * d["G"]).sum())
+        assert abs(imp["cost"] - cost) <= 1e-12 * max(1.0, cost)
+        assert np.allclose(imp["y"], d["y"], rtol=1e-12, atol=0)
+        assert cost >= pstar - 1e-12
+    assert scaled > 0                             # the column step is exercised
