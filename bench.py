@@ -382,7 +382,9 @@ def colour10m_mode(args) -> int:
 def ablation_mode(args) -> int:
     """Momentum / kernel ablation on the 128x128 grids (seeds 21, 22), eta =
     0.1, lambda = 1: every row-update variant run to a 1% certified relative
-    gap (cap 20000 iterations, certificate every 50)."""
+    gap (cap 20000 iterations, certificate every 50); the last iterate's
+    state plan is also rounded onto Pi(r, c), the feasible cost the ablation
+    compares."""
     import numpy as np
     import torch
     from paper_2609_33814_amd import bdrs, inputs
@@ -399,8 +401,10 @@ def ablation_mode(args) -> int:
         ok, ce = sv.solve(0.01, cap, CERT_EVERY)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        rd = sv.round()   # feasible plan of the last iterate (two-sided rounding), outside the timing
         out[name] = {"reached": bool(ok), "iterations": int(ce["k"]) + 1, "seconds": round(dt, 4),
-                     "rel_gap_best": ce["rel_gap_best"], "U_best": ce["U_best"], "L_best": ce["L_best"]}
+                     "rel_gap_best": ce["rel_gap_best"], "U_best": ce["U_best"], "L_best": ce["L_best"],
+                     "rounded_cost": rd["cost"], "rounded_rel_gap": (rd["cost"] - ce["L_best"]) / rd["cost"]}
         print(f"[bench] {name}: {out[name]}", flush=True)
         sv.close()
     line = {

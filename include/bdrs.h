@@ -242,6 +242,29 @@ BDRS_API bdrs_status bdrs_plan(bdrs_solver s, double *bary, double *row_marg, do
                                bdrs_plan_stats *stats);
 
 /*
+ * Feasible plan from the state plan X^k by the two-sided rounding of
+ * Altschuler, Weed and Rigollet (2017, Algorithm 2), which the momentum /
+ * kernel ablation applies to every method: rows scaled down to r
+ * (x = min(1, r / X 1)), then columns down to c (y = min(1, c / X'^T 1)),
+ * then the missing mass e_r e_c^T / ||e_r||_1 added.  The result G lies in
+ * Pi(r, c), so <C, G> is an upper bound of the optimum for any iterate.
+ * Three sweeps at the plan's temperature (the last one cost-weighted) and
+ * float64 sums; e_r^T C e_c in closed form for the squared Euclidean cost.
+ */
+typedef struct {
+  int64_t k;             /* finished iterations (the plan rounded is X^k) */
+  double eps;            /* temperature of its kernel, eta / (lambda k) */
+  double cost;           /* <C, G> */
+  double cost_clipped;   /* <C, diag(x) X diag(y)>, the part before the added mass */
+  double mass_moved;     /* ||e_r||_1 = ||e_c||_1 */
+} bdrs_round_stats;
+
+/* Rounds the solver's current state plan (host output).  BDRS_E_STATE
+ * before the first iteration.  Uses the solver's sweep buffers, not its
+ * dual state or hints.  Synchronises the stream. */
+BDRS_API bdrs_status bdrs_round(bdrs_solver s, bdrs_round_stats *out);
+
+/*
  * Batched solving (many independent problems in one set of launches).
  * The problems are solver objects from bdrs_create (each with its own
  * workspace), all with the same dim, all at an iteration count that is a

@@ -37,6 +37,7 @@ EXPORTS = [
     "bdrs_server_wait", "bdrs_server_stats", "bdrs_server_now", "bdrs_server_destroy",
     "bdrs_get_hints", "bdrs_set_hints", "bdrs_autotune_workspace_size", "bdrs_autotune",
     "bdrs_tune_set", "bdrs_tune_get", "bdrs_tune_clear", "bdrs_plan", "bdrs_server_set_policy",
+    "bdrs_round",
 ]
 
 
@@ -96,6 +97,16 @@ class PlanStats(ctypes.Structure):
         ("row_max_abs", ctypes.c_double), ("col_max_abs", ctypes.c_double),
         ("row_max_rel", ctypes.c_double), ("col_max_rel", ctypes.c_double),
         ("mass", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class RoundStats(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int64), ("eps", ctypes.c_double), ("cost", ctypes.c_double),
+        ("cost_clipped", ctypes.c_double), ("mass_moved", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -165,6 +176,7 @@ def lib() -> ctypes.CDLL:
         L.bdrs_tune_clear.argtypes = []
         L.bdrs_plan.argtypes = [vp, vp, vp, vp, P(PlanStats)]
         L.bdrs_server_set_policy.argtypes = [vp, ctypes.c_double]
+        L.bdrs_round.argtypes = [vp, P(RoundStats)]
         L.bdrs_last_error.restype = ctypes.c_char_p
         L.bdrs_version.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -298,6 +310,12 @@ class Solver:
         st = PlanStats()
         check(lib().bdrs_plan(self._h, _ptr(b), _ptr(rm), _ptr(cm), ctypes.byref(st)))
         return dict(stats=st.as_dict(), bary=b, row=rm, col=cm)
+
+    def round(self) -> dict:
+        """Cost of the two-sided rounding of the current state plan onto Pi(r, c)."""
+        st = RoundStats()
+        check(lib().bdrs_round(self._h, ctypes.byref(st)))
+        return st.as_dict()
 
     def profile(self, enable: bool) -> None:
         check(lib().bdrs_profile(self._h, 1 if enable else 0))

@@ -1022,6 +1022,44 @@ bdrs_status bdrs_plan(bdrs_solver s, double* bary, double* row_marg, double* col
   return repack(s);
 }
 
+bdrs_status bdrs_round(bdrs_solver s, bdrs_round_stats* out) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  if (!out) return fail(BDRS_E_INVALID, "out is NULL");
+  bdrs_status st = sync_k(s);
+  if (st != BDRS_OK) return st;
+  if (s->k < 1) return fail(BDRS_E_STATE, "rounding needs at least one finished iteration");
+  const LaunchCtx& c = s->ctx;
+  const double eps = s->prm.eta / (s->prm.lambda * (double)s->k);  // the state plan's kernel
+  hipError_t e;
+  // 1: row sums of X and x = min(1, r / X 1)
+  if ((e = launch_pack_state(c, false, eps)) != hipSuccess) return hip_status(e, "pack beta");
+  if ((e = sweep(s, false, false, s->L.splits_row, eps)) != hipSuccess) return hip_status(e, "row sweep");
+  if ((e = launch_finish(c, false, kFinishRound1, s->L.splits_row, eps, nullptr, 0)) != hipSuccess)
+    return hip_status(e, "row finish");
+  // 2: column sums of diag(x) X and y = min(1, c / .)
+  if ((e = launch_pack_state(c, true, eps, true)) != hipSuccess) return hip_status(e, "pack alpha x");
+  if ((e = sweep(s, true, false, s->L.splits_col, eps)) != hipSuccess) return hip_status(e, "column sweep");
+  if ((e = launch_finish(c, true, kFinishRound2, s->L.splits_col, eps, nullptr, 0)) != hipSuccess)
+    return hip_status(e, "column finish");
+  // 3: row sums and cost of diag(x) X diag(y)
+  if ((e = launch_pack_state(c, false, eps, true)) != hipSuccess) return hip_status(e, "pack beta y");
+  if ((e = sweep(s, false, true, s->L.splits_row, eps)) != hipSuccess) return hip_status(e, "cost sweep");
+  if ((e = launch_finish(c, false, kFinishRound3, s->L.splits_row, eps, nullptr, 0)) != hipSuccess)
+    return hip_status(e, "cost finish");
+  if ((e = launch_round_reduce(c)) != hipSuccess) return hip_status(e, "reduce");
+  double h[4];
+  HIPCHK(hipMemcpyAsync(h, c.plan_stats + 8, sizeof h, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  out->k = s->k;
+  out->eps = eps;
+  out->cost = h[0];
+  out->cost_clipped = h[1];
+  out->mass_moved = h[2];
+  s->packed_rows = false;
+  if (!std::isfinite(h[0])) return fail(BDRS_E_NUMERIC, "non-finite rounded cost");
+  return repack(s);
+}
+
 bdrs_status bdrs_get_hints(bdrs_solver s, int32_t* row_hint, int32_t* col_hint) {
   if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
   const LaunchCtx& c = s->ctx;

@@ -124,7 +124,10 @@ enum FinishKind {
   kFinishRepair = 4,    // repair deficits p_i
   kFinishCertOnly = 5,  // Algorithm 2 column statistics of the last finished iteration
   kFinishPlanRow = 6,   // state plan: row sums and barycentric projection (bary partials)
-  kFinishPlanCol = 7    // state plan: column sums
+  kFinishPlanCol = 7,   // state plan: column sums
+  kFinishRound1 = 8,    // rounding: row factors x = min(1, r / X 1)
+  kFinishRound2 = 9,    // rounding: column factors y = min(1, c / X'^T 1) and column deficits
+  kFinishRound3 = 10    // rounding: row deficits and the cost of the scaled plan (cert partials)
 };
 
 struct LaunchCtx {
@@ -162,8 +165,10 @@ hipError_t launch_advance(Ctrl* ctrl, int n, hipStream_t s);
 hipError_t launch_prologue(const LaunchCtx& c);                       // lt and A_C for iteration k
 hipError_t launch_pack(const LaunchCtx& c, bool transpose, const double* w, double eps);
 hipError_t launch_pack_rows_from_lah(const LaunchCtx& c, double eps);
-// state plan: input side packed from the state (columns: log beta, rows: log alpha)
-hipError_t launch_pack_state(const LaunchCtx& c, bool transpose, double eps);
+// state plan: input side packed from the state (columns: log beta, rows: log alpha),
+// plus the rounding's log factors (plan_col / plan_row) when with_factors
+hipError_t launch_pack_state(const LaunchCtx& c, bool transpose, double eps, bool with_factors = false);
+hipError_t launch_round_reduce(const LaunchCtx& c);
 // row sweep accumulating the input coordinates (barycentric projection)
 hipError_t launch_sweep_bary(const LaunchCtx& c, int splits, double eps);
 hipError_t launch_plan_stats(const LaunchCtx& c);

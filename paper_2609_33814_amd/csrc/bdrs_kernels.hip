@@ -112,9 +112,9 @@ typedef __attribute__((address_space(1))) const Ctrl gctrl;
 
 typedef __attribute__((address_space(1))) const TileRec gtile;
 
-// Points of a tile per group: the tile data of one group (offsets and weights,
-// 8 (D + 1) floats) is loaded into scalar registers while the previous group
-// is being computed.
+// Points of a tile per group: the tile data of one group (8 D offsets into
+// scalar registers, 8 weights into vector registers by broadcast loads) is
+// requested while the previous group is being computed.
 constexpr int kGroup = 8;
 
 // The fields of a tile record the sweep uses (dimensions < D).
@@ -147,11 +147,12 @@ struct Group {
   float a[kGroup];
 };
 
+// Group g of a tile whose offsets start at offs_t ([D][64]) and weights at a_t.
 template <int D>
-__device__ __forceinline__ Group<D> load_group(gfloat* __restrict__ in_off, gfloat* __restrict__ in_A, int t, int g) {
+__device__ __forceinline__ Group<D> load_group(gfloat* __restrict__ offs_t, gfloat* __restrict__ a_t, int g) {
   Group<D> r;
-  gfloat* offs = in_off + (size_t)t * D * kTile + g * kGroup;
-  gfloat* aq = in_A + (size_t)t * kTile + g * kGroup;
+  gfloat* offs = offs_t + g * kGroup;
+  gfloat* aq = a_t + g * kGroup;
 #pragma unroll
   for (int d = 0; d < D; ++d)
 #pragma unroll
@@ -231,13 +232,23 @@ __device__ __forceinline__ void sweep_block(
     return;
   }
 
+  double Mth = M + kThresh;                     // the exact-max gate, updated with M
+  // The weights are read with broadcast vector loads (a lane-dependent zero in
+  // the address), which leaves the scalar path to the offsets and tile
+  // records: moving either kind the other way measured slower.
+  const int lane0 = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
   TileVals<D> cur = load_tile<D>(in_tile + t0);
-  Group<D> grp = load_group<D>(in_off, in_A, t0, 0);
+  Group<D> grp = load_group<D>(in_off + (size_t)t0 * D * kTile, in_A + (size_t)t0 * kTile + lane0, 0);
   for (int t = t0; t < t1; ++t) {
     const int tn = min(t + 1, t1 - 1);         // next tile (the last one re-reads itself)
-    if (cur.amax == -INFINITY) {               // tile carries no mass (masked weights)
+    // tile addresses computed before any lane-dependent branch
+    gfloat* __restrict__ offs_t = in_off + (size_t)t * D * kTile;
+    gfloat* __restrict__ a_t = in_A + (size_t)t * kTile + lane0;
+    gfloat* __restrict__ offs_n = in_off + (size_t)tn * D * kTile;
+    gfloat* __restrict__ a_n = in_A + (size_t)tn * kTile + lane0;
+    if (__double_as_longlong(cur.amax) == (long long)0xFFF0000000000000ULL) {  // -inf: no mass
       cur = load_tile<D>(in_tile + tn);
-      grp = load_group<D>(in_off, in_A, tn, 0);
+      grp = load_group<D>(offs_n, a_n, 0);
       continue;
     }
     float a[D], B[D], na = 0.0f;
@@ -255,17 +266,17 @@ __device__ __forceinline__ void sweep_block(
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const float g = cur.gam[d], rad = cur.rad[d];
-      const float bs = fminf(fmaxf(fmaf(g, inv2kap, a[d]), -rad), rad);
+      const float bs = __builtin_amdgcn_fmed3f(fmaf(g, inv2kap, a[d]), -rad, rad);  // clamp to the box
       const float df = a[d] - bs;
       ubf = fmaf(g, bs, ubf);
       ubf = fmaf(-kap2f, df * df, ubf);
     }
     const double ub = cur.alpha + (double)ubf;
 
-    if (ub > M + kThresh) {
+    if (ub > Mth) {
       // exact maximum of this tile for the lanes whose bound exceeds the window
-      gfloat* __restrict__ offs = in_off + (size_t)t * D * kTile;
-      gfloat* __restrict__ Aq = in_A + (size_t)t * kTile;
+      gfloat* __restrict__ offs = offs_t;
+      gfloat* __restrict__ Aq = a_t;
       float tm = -INFINITY;
       int qi = 0;
 #pragma unroll 8
@@ -288,6 +299,7 @@ __device__ __forceinline__ void sweep_block(
           for (int d = 0; d < D; ++d) V[d] *= sc;
         }
         M = tmd;
+        Mth = M + kThresh;
         J = t * kTile + qi;
       }
     }
@@ -301,8 +313,8 @@ __device__ __forceinline__ void sweep_block(
 #pragma unroll
     for (int g = 0; g < kTile / kGroup; ++g) {
       // request the next group (the first group of the next tile after the last)
-      const Group<D> nx = (g + 1 < kTile / kGroup) ? load_group<D>(in_off, in_A, t, g + 1)
-                                                  : load_group<D>(in_off, in_A, tn, 0);
+      const Group<D> nx = (g + 1 < kTile / kGroup) ? load_group<D>(offs_t, a_t, g + 1)
+                                                  : load_group<D>(offs_n, a_n, 0);
 #pragma unroll
       for (int u = 0; u < kGroup; ++u) {
         float z = cm;
@@ -605,6 +617,31 @@ __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, 
     if (real) c.plan_col[p] = exp(c.st.lb1[p] + mg.lse);
     return;
   }
+  // two-sided rounding of the state plan (Altschuler, Weed and Rigollet 2017, Algorithm 2)
+  if (kind == kFinishRound1) {
+    // log x_i = min(0, log r_i - log (X 1)_i)
+    if (real) c.plan_row[p] = fmin(0.0, out.logmarg[p] - (c.st.la[p] + mg.lse));
+    return;
+  }
+  if (kind == kFinishRound2) {
+    // X' = diag(x) X: log y_j = min(0, log c_j - log (X'^T 1)_j); deficit c_j - y_j (X'^T 1)_j
+    if (real) {
+      const double lcol = c.st.lb1[p] + mg.lse;
+      const double ly = fmin(0.0, out.logmarg[p] - lcol);
+      c.plan_col[p] = ly;
+      c.st.mu[p] = out.marg[p] - exp(lcol + ly);
+    }
+    return;
+  }
+  if (kind == kFinishRound3) {
+    // X'' = diag(x) X diag(y): row deficit r_i - (X'' 1)_i and sum_j X''_ij C_ij
+    if (real) {
+      const double row2 = exp(c.st.la[p] + c.plan_row[p] + mg.lse);
+      c.plan_row[p] = out.marg[p] - row2;
+      c.st.pvec[p] = row2 * ctrl->scale * mg.N / mg.S;
+    }
+    return;
+  }
   if (kind == kFinishCertOnly) {
     // Algorithm 2 for the last finished iteration k-1 (k has been advanced)
     if (real) {
@@ -728,13 +765,16 @@ __global__ __launch_bounds__(kBlock) void k_pack_rows(LaunchCtx c, double eps) {
 
 // State-plan weights of the input side: log beta^{k-1} on the columns (row sums
 // and barycentres), log alpha^{k-1} on the rows (column sums), at temperature eps.
-__global__ __launch_bounds__(kBlock) void k_pack_state(LaunchCtx c, int transpose, double eps) {
+__global__ __launch_bounds__(kBlock) void k_pack_state(LaunchCtx c, int transpose, double eps, int with_factors) {
   const SideDev& in = transpose ? c.rows : c.cols;
   const int p = blockIdx.x * kBlock + threadIdx.x;
   if (p >= in.np) return;
   const double kap2 = kLog2eD * c.ctrl->scale / eps;
   const double* w = transpose ? c.st.la : c.st.lb1;
-  pack_weight(in, c.dim, p, p < in.count ? w[p] : 0.0, kap2);
+  const double* f = transpose ? c.plan_row : c.plan_col;
+  double v = 0.0;
+  if (p < in.count) v = with_factors ? w[p] + f[p] : w[p];
+  pack_weight(in, c.dim, p, v, kap2);
 }
 
 // Marginal-error statistics of the state plan (float64): per block partial
@@ -966,6 +1006,69 @@ __global__ __launch_bounds__(kBlock) void k_repair_final(LaunchCtx c) {
   }
 }
 
+// Rounded cost: sum_i cost_i + e_r^T C e_c / ||e_r||_1 with the squared
+// Euclidean closed form e_r^T C e_c = s [ (sum e_c)(sum e_r |x|^2) +
+// (sum e_r)(sum e_c |y|^2) - 2 (sum e_r x).(sum e_c y) ].  Row deficits in
+// plan_row, row costs in pvec, column deficits in mu (kFinishRound3 / 2).
+__global__ __launch_bounds__(kBlock) void k_round_partial(LaunchCtx c) {
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int stride = gridDim.x * kBlock;
+  const int dim = c.dim;
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < c.rows.count; p += stride) {
+    const double er = c.plan_row[p];
+    double n2 = 0.0;
+    for (int d = 0; d < dim; ++d) {
+      const double xd = c.rows.abs[(size_t)d * c.rows.np + p];
+      n2 += xd * xd;
+      v[3 + d] += er * xd;
+    }
+    v[0] += er;
+    v[1] += c.st.pvec[p];
+    v[2] += er * n2;
+  }
+  block_reduce_store(v, 6, c.cert_part + (size_t)blockIdx.x * 8);
+  __syncthreads();
+  double w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < c.cols.count; p += stride) {
+    const double ec = c.st.mu[p];
+    double n2 = 0.0;
+    for (int d = 0; d < dim; ++d) {
+      const double yd = c.cols.abs[(size_t)d * c.cols.np + p];
+      n2 += yd * yd;
+      w[3 + d] += ec * yd;
+    }
+    w[0] += ec;
+    w[2] += ec * n2;
+  }
+  block_reduce_store(w, 6, c.cert_part + ((size_t)gridDim.x + blockIdx.x) * 8);
+}
+
+__global__ __launch_bounds__(kBlock) void k_round_final(LaunchCtx c) {
+  double v[6] = {0, 0, 0, 0, 0, 0}, w[6] = {0, 0, 0, 0, 0, 0};
+  const int G = c.cert_blocks;
+  for (int b = threadIdx.x; b < G; b += kBlock)
+    for (int i = 0; i < 6; ++i) {
+      v[i] += c.cert_part[(size_t)b * 8 + i];
+      w[i] += c.cert_part[(size_t)(G + b) * 8 + i];
+    }
+  __shared__ double tv[8], tw[8];
+  block_reduce_store(v, 6, tv);
+  __syncthreads();
+  block_reduce_store(w, 6, tw);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double dot = 0.0;
+    for (int d = 0; d < c.dim; ++d) dot += tv[3 + d] * tw[3 + d];
+    const double erCec = c.ctrl->scale * (tw[0] * tv[2] + tv[0] * tw[2] - 2.0 * dot);
+    const double mass = tv[0];
+    double* o = c.plan_stats;
+    o[8] = tv[1] + (mass > 0.0 ? erCec / mass : 0.0);   // <C, G>
+    o[9] = tv[1];                                       // <C, X''>
+    o[10] = mass;                                       // ||e_r||_1
+    o[11] = tw[0];                                      // ||e_c||_1 (equals ||e_r||_1)
+  }
+}
+
 __global__ void k_scatter(const double* __restrict__ src, const int* __restrict__ perm, int count,
                           double* __restrict__ dst) {
   const int p = blockIdx.x * kBlock + threadIdx.x;
@@ -1121,9 +1224,17 @@ hipError_t launch_pack_rows_from_lah(const LaunchCtx& c, double eps) {
   return hipGetLastError();
 }
 
-hipError_t launch_pack_state(const LaunchCtx& c, bool transpose, double eps) {
+hipError_t launch_pack_state(const LaunchCtx& c, bool transpose, double eps, bool with_factors) {
   const SideDev& in = transpose ? c.rows : c.cols;
-  hipLaunchKernelGGL(k_pack_state, dim3(in.np / kBlock), dim3(kBlock), 0, c.stream, c, transpose ? 1 : 0, eps);
+  hipLaunchKernelGGL(k_pack_state, dim3(in.np / kBlock), dim3(kBlock), 0, c.stream, c, transpose ? 1 : 0, eps,
+                     with_factors ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_reduce(const LaunchCtx& c) {
+  // two sets of cert_blocks x 8 partials: the certificate's buffer holds both
+  hipLaunchKernelGGL(k_round_partial, dim3(c.cert_blocks), dim3(kBlock), 0, c.stream, c);
+  hipLaunchKernelGGL(k_round_final, dim3(1), dim3(kBlock), 0, c.stream, c);
   return hipGetLastError();
 }
 

@@ -138,6 +138,14 @@ def test_server_calls_reject_null_server():
     assert L.bdrs_server_set_policy(None, 1e9) == bdrs.E_INVALID
 
 
+def test_plan_and_round_reject_null_solver():
+    L = bdrs.lib()
+    st = bdrs.RoundStats()
+    assert L.bdrs_round(None, ctypes.byref(st)) == bdrs.E_INVALID
+    ps = bdrs.PlanStats()
+    assert L.bdrs_plan(None, None, None, None, ctypes.byref(ps)) == bdrs.E_INVALID
+
+
 # ----------------------------------------------------------------------------
 # tuning table (host only)
 # ----------------------------------------------------------------------------
