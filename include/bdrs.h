@@ -411,6 +411,13 @@ BDRS_API bdrs_status bdrs_tune_clear(void);
 BDRS_API bdrs_status bdrs_profile(bdrs_solver s, int32_t enable);
 BDRS_API bdrs_status bdrs_profile_read(bdrs_solver s, int64_t *sweeps, double *ms,
                                        double *entries);
+/* Entries the timed sweeps actually evaluated since the last enable: a sweep
+ * skips an input tile for a wavefront of 64 outputs when its bound puts
+ * every term of the tile below 2^-64 of each output's running maximum (such
+ * terms cannot change a float32 sum), so this can be far below the implicit
+ * m n per sweep late in a solve.  Counted per (64 outputs, 64 inputs) pair,
+ * padding included.  Synchronises the stream. */
+BDRS_API bdrs_status bdrs_profile_evaluated(bdrs_solver s, double *entries);
 
 /* Destroys the solver object (host memory only; the workspace stays the
  * caller's).  Synchronises the stream.  NULL is accepted. */

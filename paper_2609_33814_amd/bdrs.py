@@ -37,7 +37,7 @@ EXPORTS = [
     "bdrs_server_wait", "bdrs_server_stats", "bdrs_server_now", "bdrs_server_destroy",
     "bdrs_get_hints", "bdrs_set_hints", "bdrs_autotune_workspace_size", "bdrs_autotune",
     "bdrs_tune_set", "bdrs_tune_get", "bdrs_tune_clear", "bdrs_plan", "bdrs_server_set_policy",
-    "bdrs_round",
+    "bdrs_round", "bdrs_profile_evaluated",
 ]
 
 
@@ -177,6 +177,7 @@ def lib() -> ctypes.CDLL:
         L.bdrs_plan.argtypes = [vp, vp, vp, vp, P(PlanStats)]
         L.bdrs_server_set_policy.argtypes = [vp, ctypes.c_double]
         L.bdrs_round.argtypes = [vp, P(RoundStats)]
+        L.bdrs_profile_evaluated.argtypes = [vp, P(ctypes.c_double)]
         L.bdrs_last_error.restype = ctypes.c_char_p
         L.bdrs_version.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -323,7 +324,9 @@ class Solver:
     def profile_read(self) -> dict:
         n, ms, ent = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
         check(lib().bdrs_profile_read(self._h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(ent)))
-        return dict(sweeps=n.value, ms=ms.value, entries=ent.value)
+        ev = ctypes.c_double()
+        check(lib().bdrs_profile_evaluated(self._h, ctypes.byref(ev)))
+        return dict(sweeps=n.value, ms=ms.value, entries=ent.value, evaluated=ev.value)
 
     def close(self) -> None:
         if getattr(self, "_h", None):

@@ -106,10 +106,13 @@ Layout make_layout(int m, int n, int dim, int reserve_row, int reserve_col) {
   L.plan_row = take(sizeof(double) * L.R.np);
   L.plan_col = take(sizeof(double) * L.C.np);
   L.plan_stats = take(sizeof(double) * kCertSlots);
+  L.tile_total = take(sizeof(unsigned long long));
   // partial records last: every other offset is independent of the split counts
   const size_t rows_rec = (size_t)std::max(L.splits_row, reserve_row) * L.R.np;
   const size_t cols_rec = (size_t)std::max(L.splits_col, reserve_col) * L.C.np;
   L.part = take(sizeof(PartialRec) * std::max(rows_rec, cols_rec));
+  // one evaluated-tile count per (split, output wavefront) of a sweep (profiling)
+  L.tile_count = take(sizeof(unsigned) * (std::max(rows_rec, cols_rec) / kTile));
   L.total = o;
   return L;
 }
@@ -306,6 +309,8 @@ void fill_ctx(bdrs_solver s) {
   c.plan_row = (double*)(base + L.plan_row);
   c.plan_col = (double*)(base + L.plan_col);
   c.plan_stats = (double*)(base + L.plan_stats);
+  c.tile_count = nullptr;  // set for profiled sweeps only
+  c.tile_total = nullptr;
 }
 
 // reads the device iteration counter (synchronises the stream)
@@ -333,7 +338,8 @@ bdrs_status hip_status(hipError_t e, const char* what) {
   return BDRS_OK;
 }
 
-// one LSE sweep launch, bracketed by HIP events when profiling is on
+// one LSE sweep launch, bracketed by HIP events when profiling is on; a
+// profiled sweep also counts the input tiles its wavefronts evaluated
 hipError_t sweep(bdrs_solver s, bool transpose, bool cert, int splits, double eps_arg, int kofs = 0) {
   if (!s->prof) return launch_sweep(s->ctx, transpose, cert, splits, eps_arg, kofs);
   while (s->ev_pool.size() < s->ev_used + 2) {
@@ -342,10 +348,16 @@ hipError_t sweep(bdrs_solver s, bool transpose, bool cert, int splits, double ep
     if (e != hipSuccess) return e;
     s->ev_pool.push_back(ev);
   }
+  char* base = (char*)s->prm.workspace;
+  LaunchCtx c = s->ctx;
+  c.tile_count = (unsigned*)(base + s->L.tile_count);
+  c.tile_total = (unsigned long long*)(base + s->L.tile_total);
   hipEvent_t a = s->ev_pool[s->ev_used], b = s->ev_pool[s->ev_used + 1];
-  hipError_t e = hipEventRecord(a, s->ctx.stream);
-  if (e == hipSuccess) e = launch_sweep(s->ctx, transpose, cert, splits, eps_arg, kofs);
-  if (e == hipSuccess) e = hipEventRecord(b, s->ctx.stream);
+  hipError_t e = hipEventRecord(a, c.stream);
+  if (e == hipSuccess) e = launch_sweep(c, transpose, cert, splits, eps_arg, kofs);
+  if (e == hipSuccess) e = hipEventRecord(b, c.stream);
+  const int np_out = transpose ? c.cols.np : c.rows.np;
+  if (e == hipSuccess) e = launch_count_tiles(c, splits * (np_out / kTile));
   if (e == hipSuccess) {
     s->ev_used += 2;
     s->prof_sweeps += 1;
@@ -1090,7 +1102,21 @@ bdrs_status bdrs_profile(bdrs_solver s, int32_t enable) {
     s->ev_used = 0;
     s->prof_entries = 0.0;
     s->prof_sweeps = 0;
+    char* base = (char*)s->prm.workspace;
+    HIPCHK(hipMemsetAsync(base + s->L.tile_total, 0, sizeof(unsigned long long), s->ctx.stream));
+    HIPCHK(hipStreamSynchronize(s->ctx.stream));
   }
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_profile_evaluated(bdrs_solver s, double* entries) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  if (!entries) return fail(BDRS_E_INVALID, "entries is NULL");
+  unsigned long long tiles = 0;
+  HIPCHK(hipMemcpyAsync(&tiles, (char*)s->prm.workspace + s->L.tile_total, sizeof tiles, hipMemcpyDeviceToHost,
+                        s->ctx.stream));
+  HIPCHK(hipStreamSynchronize(s->ctx.stream));
+  *entries = (double)tiles * (double)kTile * (double)kTile;  // (64 outputs) x (64 inputs) per count
   return BDRS_OK;
 }
 

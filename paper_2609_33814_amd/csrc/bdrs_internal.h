@@ -145,6 +145,10 @@ struct LaunchCtx {
   double* plan_col;    // [cols.np] column sums of the state plan (tile order)
   double* plan_stats;  // [kCertSlots] marginal-error statistics
   double origin[3];    // common origin of the stored coordinates
+  // profiling only (null otherwise): one slot per sweep wavefront receiving
+  // the number of input tiles it evaluated, and their running total
+  unsigned* tile_count;
+  unsigned long long* tile_total;
 };
 
 // One work item of a batched phase: problem index into the descriptor array,
@@ -171,6 +175,8 @@ hipError_t launch_pack_state(const LaunchCtx& c, bool transpose, double eps, boo
 hipError_t launch_round_reduce(const LaunchCtx& c);
 // row sweep accumulating the input coordinates (barycentric projection)
 hipError_t launch_sweep_bary(const LaunchCtx& c, int splits, double eps);
+// adds the per-wavefront tile counts of the last sweep (n slots) to *tile_total
+hipError_t launch_count_tiles(const LaunchCtx& c, int n);
 hipError_t launch_plan_stats(const LaunchCtx& c);
 hipError_t launch_cert_reduce(const LaunchCtx& c);
 hipError_t launch_repair_pack(const LaunchCtx& c);

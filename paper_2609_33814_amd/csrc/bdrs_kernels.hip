@@ -174,7 +174,7 @@ __device__ __forceinline__ void sweep_block(
     gfloat* __restrict__ in_off, gfloat* __restrict__ in_A, gtile* __restrict__ in_tile,
     int ntiles_in, int count_in, int tps, const int* __restrict__ hint,
     PartialRec* __restrict__ part, gctrl* __restrict__ ctrl, double eps_arg, int kofs, int bx, int split,
-    bool row_sweep) {
+    bool row_sweep, unsigned* __restrict__ tile_count, int slot) {
   constexpr bool CERT = MODE == kSweepCert;
   constexpr bool BARY = MODE == kSweepBary;
   const int p = bx * kSweepBlock + threadIdx.x;
@@ -220,7 +220,9 @@ __device__ __forceinline__ void sweep_block(
   float V[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) V[d] = 0.0f;
+  int evaluated = 0;  // input tiles this wavefront evaluated (the same on every lane)
   if (t0 >= t1) {
+    if (tile_count && (threadIdx.x & (kTile - 1)) == 0) tile_count[slot] = 0;
     if (BARY) {
       PartialBary* pb = reinterpret_cast<PartialBary*>(part) + (size_t)split * np_out + p;
       pb->M = M;
@@ -233,6 +235,7 @@ __device__ __forceinline__ void sweep_block(
   }
 
   double Mth = M + kThresh;                     // the exact-max gate, updated with M
+  double Mlo = M - kThresh;                     // the skip gate, updated with M
   // The weights are read with broadcast vector loads (a lane-dependent zero in
   // the address), which leaves the scalar path to the offsets and tile
   // records: moving either kind the other way measured slower.
@@ -272,6 +275,14 @@ __device__ __forceinline__ void sweep_block(
       ubf = fmaf(-kap2f, df * df, ubf);
     }
     const double ub = cur.alpha + (double)ubf;
+    // every term of this tile lies below 2^-64 of the running maximum on every
+    // lane: the tile cannot change any sum in float32, so it is skipped
+    if (__all(ub < Mlo)) {
+      cur = load_tile<D>(in_tile + tn);
+      grp = load_group<D>(offs_n, a_n, 0);
+      continue;
+    }
+    ++evaluated;
 
     if (ub > Mth) {
       // exact maximum of this tile for the lanes whose bound exceeds the window
@@ -300,6 +311,7 @@ __device__ __forceinline__ void sweep_block(
         }
         M = tmd;
         Mth = M + kThresh;
+        Mlo = M - kThresh;
         J = t * kTile + qi;
       }
     }
@@ -353,6 +365,7 @@ __device__ __forceinline__ void sweep_block(
     }
     cur = nxt;
   }
+  if (tile_count && (threadIdx.x & (kTile - 1)) == 0) tile_count[slot] = (unsigned)evaluated;
   if (BARY) {
     PartialBary* pb = reinterpret_cast<PartialBary*>(part) + (size_t)split * np_out + p;
     pb->M = M;
@@ -374,10 +387,12 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(
     const float* __restrict__ out_abs, int np_out,
     const float* __restrict__ in_off, const float* __restrict__ in_A, const TileRec* __restrict__ in_tile,
     int ntiles_in, int count_in, int tps, const int* __restrict__ hint,
-    PartialRec* __restrict__ part, const Ctrl* __restrict__ ctrl, double eps_arg, int kofs, int row_sweep) {
+    PartialRec* __restrict__ part, const Ctrl* __restrict__ ctrl, double eps_arg, int kofs, int row_sweep,
+    unsigned* __restrict__ tile_count) {
+  const int slot = (blockIdx.y * gridDim.x + blockIdx.x) * (kSweepBlock / kTile) + threadIdx.x / kTile;
   sweep_block<D, MODE>((gfloat*)out_abs, np_out, (gfloat*)in_off, (gfloat*)in_A, (gtile*)in_tile, ntiles_in,
                        count_in, tps, hint, part, (gctrl*)ctrl, eps_arg, kofs, blockIdx.x, blockIdx.y,
-                       row_sweep != 0);
+                       row_sweep != 0, tile_count, slot);
 }
 
 // Batched sweep: block i runs work item i = (problem, block of outputs, split)
@@ -395,7 +410,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep_batch(const BatchItem* __
   const int tps = (in.ntiles + splits - 1) / splits;
   sweep_block<D, MODE>((gfloat*)out.abs, out.np, (gfloat*)in.off, (gfloat*)in.A, (gtile*)in.tile, in.ntiles,
                        in.count, tps, out.hint, c.part.rec, (gctrl*)c.ctrl, -1.0, kofs, it.blk, it.split,
-                       transpose == 0);
+                       transpose == 0, nullptr, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1069,6 +1084,22 @@ __global__ __launch_bounds__(kBlock) void k_round_final(LaunchCtx c) {
   }
 }
 
+// Adds the per-wavefront tile counts of one sweep to the running total (one
+// block, fixed order: profiling only).
+__global__ __launch_bounds__(kBlock) void k_count_tiles(const unsigned* __restrict__ count, int n,
+                                                        unsigned long long* __restrict__ total) {
+  __shared__ unsigned long long part[kBlock];
+  unsigned long long v = 0;
+  for (int i = threadIdx.x; i < n; i += kBlock) v += count[i];
+  part[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tsum = 0;
+    for (int i = 0; i < kBlock; ++i) tsum += part[i];
+    *total += tsum;
+  }
+}
+
 __global__ void k_scatter(const double* __restrict__ src, const int* __restrict__ perm, int count,
                           double* __restrict__ dst) {
   const int p = blockIdx.x * kBlock + threadIdx.x;
@@ -1167,7 +1198,7 @@ hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int split
 #define BDRS_SWEEP(DD, CC)                                                                          \
   hipLaunchKernelGGL((k_sweep<DD, CC>), grid, dim3(kSweepBlock), 0, c.stream, out.abs, out.np, in.off,  \
                      in.A, in.tile, in.ntiles, in.count, tps, out.hint,                                  \
-                     c.part.rec, c.ctrl, eps_arg, kofs, transpose ? 0 : 1)
+                     c.part.rec, c.ctrl, eps_arg, kofs, transpose ? 0 : 1, c.tile_count)
   switch (c.dim * 2 + (cert ? 1 : 0)) {
     case 2: BDRS_SWEEP(1, kSweepPlain); break;
     case 3: BDRS_SWEEP(1, kSweepCert); break;
@@ -1188,7 +1219,8 @@ hipError_t launch_sweep_bary(const LaunchCtx& c, int splits, double eps) {
   dim3 grid(out.np / kSweepBlock, splits);
 #define BDRS_SWEEP(DD)                                                                                  \
   hipLaunchKernelGGL((k_sweep<DD, kSweepBary>), grid, dim3(kSweepBlock), 0, c.stream, out.abs, out.np,   \
-                     in.off, in.A, in.tile, in.ntiles, in.count, tps, out.hint, c.part.rec, c.ctrl, eps, 0, 1)
+                     in.off, in.A, in.tile, in.ntiles, in.count, tps, out.hint, c.part.rec, c.ctrl, eps, 0, 1,    \
+                     c.tile_count)
   switch (c.dim) {
     case 1: BDRS_SWEEP(1); break;
     case 2: BDRS_SWEEP(2); break;
@@ -1221,6 +1253,12 @@ hipError_t launch_pack(const LaunchCtx& c, bool transpose, const double* w, doub
 
 hipError_t launch_pack_rows_from_lah(const LaunchCtx& c, double eps) {
   hipLaunchKernelGGL(k_pack_rows, dim3(c.rows.np / kBlock), dim3(kBlock), 0, c.stream, c, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_tiles(const LaunchCtx& c, int n) {
+  if (!c.tile_count || !c.tile_total || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_count_tiles, dim3(1), dim3(kBlock), 0, c.stream, c.tile_count, n, c.tile_total);
   return hipGetLastError();
 }
 

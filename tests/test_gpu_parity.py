@@ -286,3 +286,33 @@ def test_full_size_colour_sampled_rows():
             ref = np.concatenate([lse.implicit_lse(src, dst, prob.cost_scale, eps, w, rows=rows[a:a + 16])
                                   for a in range(0, rows.size, 16)])
             assert rel_err(got, ref) <= SWEEP_TOL, (transpose, eps)
+
+
+def test_skipped_tiles_late_in_a_solve():
+    """Late in a solve most input tiles lie far below each output's running
+    maximum and are skipped; the sweeps the solver ran there (with its own
+    warm-start hints) still match the oracle on sampled rows and columns."""
+    prob = inputs.c2_problem()
+    eta = 0.1
+    sv = solver_for(prob, eta=eta)
+    sv.step(500)
+    sv.profile(True)
+    sv.step(100)
+    p = sv.profile_read()
+    sv.profile(False)
+    frac = p["evaluated"] / p["entries"]
+    assert 0.0 < frac < 0.5, frac
+    gs = sv.get_state()
+    assert gs["k"] == 600
+    eps = alg1.schedule(eta, 1.0, gs["k"] - 1)
+    rng = np.random.default_rng(37)
+    rows = rng.choice(prob.m, 256, replace=False)
+    lt = gs["lt"].cpu().numpy()
+    lse_gpu = np.log(prob.r[rows]) - gs["lah"].cpu().numpy()[rows]
+    lse_ref = lse.implicit_lse(prob.x, prob.y, prob.cost_scale, eps, lt, rows=rows)
+    assert rel_err(lse_gpu, lse_ref) <= SWEEP_TOL, rel_err(lse_gpu, lse_ref)
+    cols = rng.choice(prob.n, 256, replace=False)
+    lah = gs["lah"].cpu().numpy()
+    lse_gpu = np.log(prob.c[cols]) - gs["lbh"].cpu().numpy()[cols]
+    lse_ref = lse.implicit_lse(prob.y, prob.x, prob.cost_scale, eps, lah, rows=cols)
+    assert rel_err(lse_gpu, lse_ref) <= SWEEP_TOL, rel_err(lse_gpu, lse_ref)
