@@ -487,15 +487,25 @@ def main() -> int:
     for _ in range(args.warmup):
         sv.solve(0.0, CERT_EVERY, CERT_EVERY)
     torch.cuda.synchronize()
-    sv.profile(True)
+    start_state, start_hints = sv.get_state(), sv.get_hints()
     t0 = time.perf_counter()
     last = None
     for _ in range(args.steps):
         _, last = sv.solve(0.0, CERT_EVERY, CERT_EVERY)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # the same steps again from the same state, each sweep bracketed by HIP
+    # events (kernel time) and followed by its evaluated-tile count
+    sv.set_state(start_state)
+    sv.set_hints(start_hints)
+    sv.profile(True)
+    last_prof = None
+    for _ in range(args.steps):
+        _, last_prof = sv.solve(0.0, CERT_EVERY, CERT_EVERY)
     prof = sv.profile_read()
     sv.profile(False)
+    if last is not None and last_prof["rel_gap"] != last["rel_gap"]:
+        raise RuntimeError("the profiled replay diverged from the timed steps")
     sweeps = args.steps * CERT_EVERY * 2
     entries = sweeps * prob.m * prob.n
     value = entries / wall / 1e9

@@ -366,7 +366,7 @@ BDRS_API bdrs_status bdrs_server_destroy(bdrs_server s);
  * the exact shape (dim, m, n) holds the chosen split counts; every layout
  * (bdrs_workspace_size, bdrs_create, the server's admission) made after an
  * entry exists uses it, and shapes without an entry use a built-in heuristic
- * (about 4096 wavefronts per sweep, at least 4 input tiles per split).  A
+ * (about 16384 wavefronts per sweep, at least 4 input tiles per split).  A
  * workspace must be sized with the same table in effect as the bdrs_create
  * that uses it.  The table is guarded by a mutex.
  */
@@ -385,7 +385,8 @@ typedef struct {
 BDRS_API bdrs_status bdrs_autotune_workspace_size(const bdrs_params *p, size_t *bytes);
 /* Times candidate split counts for the problem in *p (same fields and
  * checks as bdrs_create; workspace of bdrs_autotune_workspace_size bytes):
- * runs a few iterations of Algorithm 1 to reach a typical state, then
+ * runs min(500, max(10, 2e13 / (2 m n))) iterations of Algorithm 1 to reach
+ * the low-temperature regime where a solve spends most sweeps, then
  * `rounds` rounds that each time every candidate's row and column sweep
  * (with its epilogue) once with HIP events on p->stream, interleaved so the
  * drift of the state affects every candidate alike.  The candidate with

@@ -19,7 +19,7 @@ constexpr int kCertSlots = 16;    // doubles in a certificate record
 
 // (output wavefront, split) pairs a sweep aims for: 4 per SIMD on 256 CUs
 #ifndef BDRS_TARGET_WAVES
-#define BDRS_TARGET_WAVES 4096
+#define BDRS_TARGET_WAVES 16384
 #endif
 
 // Device-resident control block of one solver: the iteration counter lives

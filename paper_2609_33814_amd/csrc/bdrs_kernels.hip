@@ -1179,8 +1179,11 @@ hipError_t launch_cert_batch(const BatchItem* items, int nitems, const int* prob
 }
 
 int choose_splits(int np_out, int ntiles_in) {
-  // enough (output wave, split) pairs to give every SIMD of the 256 CUs a few
-  // waves, but at least 4 tiles per split so the per-split set-up stays small
+  // enough (output wave, split) pairs to give every SIMD of the 256 CUs many
+  // waves (skipped tiles make the work per pair uneven, so finer pairs balance
+  // better), but at least 4 tiles per split so the per-split set-up stays
+  // small; the partial records stay below target * 64 records plus one per
+  // output
   const int out_waves = (np_out + kTile - 1) / kTile;
   int s = (BDRS_TARGET_WAVES + out_waves - 1) / out_waves;
   const int max_s = (ntiles_in + 3) / 4;

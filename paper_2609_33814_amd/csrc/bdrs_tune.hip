@@ -141,8 +141,12 @@ bdrs_status bdrs_autotune(const bdrs_params* p, int32_t rounds, bdrs_tune_entry*
   hipError_t e = hipSuccess;
   for (auto& x : ev)
     if (e == hipSuccess) e = hipEventCreate(&x);
-  // warm-up: a few iterations bring the dual state to a typical regime
-  if (e == hipSuccess && (st = bdrs_step(s, 10)) != BDRS_OK) e = hipErrorUnknown;
+  // warm-up into the regime where a solve spends most of its sweeps (at low
+  // temperature most input tiles are skipped): up to 500 iterations, at most
+  // about 2e13 implicit entries, at least 10
+  const double per_iter = 2.0 * (double)p->m * (double)p->n;
+  const int warm = (int)std::max(10.0, std::min(500.0, std::floor(2e13 / per_iter)));
+  if (e == hipSuccess && (st = bdrs_step(s, warm)) != BDRS_OK) e = hipErrorUnknown;
   LaunchCtx& c = s->ctx;
   for (int r = 0; r < rounds && e == hipSuccess; ++r) {
     for (int i = 0; i < K && e == hipSuccess; ++i) {

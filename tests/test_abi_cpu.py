@@ -161,13 +161,13 @@ def saved_table():
 
 def test_tune_table_roundtrip_and_layout(saved_table, tmp_path):
     base = bdrs.workspace_size(16384, 16384, 2)
-    bdrs.tune_set(dict(dim=2, m=16384, n=16384, splits_row=64, splits_col=2))
+    bdrs.tune_set(dict(dim=2, m=16384, n=16384, splits_row=256, splits_col=2))
     tab = bdrs.tune_table()
-    assert len(tab) == 1 and tab[0]["splits_row"] == 64 and tab[0]["splits_col"] == 2
-    # 64 splits x 16384 outputs of 24-byte partial records dominate the workspace
-    assert bdrs.workspace_size(16384, 16384, 2) >= 64 * 16384 * 24 > base
+    assert len(tab) == 1 and tab[0]["splits_row"] == 256 and tab[0]["splits_col"] == 2
+    # 256 splits x 16384 outputs of 24-byte partial records dominate the workspace
+    assert bdrs.workspace_size(16384, 16384, 2) >= 256 * 16384 * 24 > base
     # other shapes are untouched
-    assert bdrs.workspace_size(16384, 16385, 2) < 64 * 16384 * 24
+    assert bdrs.workspace_size(16384, 16385, 2) < 256 * 16384 * 24
     # replace, not append
     bdrs.tune_set(dict(dim=2, m=16384, n=16384, splits_row=3, splits_col=3))
     assert len(bdrs.tune_table()) == 1 and bdrs.tune_table()[0]["splits_row"] == 3
