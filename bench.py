@@ -37,20 +37,22 @@ EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters
                      # 64 lane-ops/CU/cycle ceiling, which a 2-slot exp would put above 100%
 
 
-# HBM traffic of one k_sweep<2,false> launch on the 128x128 grids (16 splits per
-# direction): rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE per dispatch, each scaled
-# by what the counter reads for a 256 MiB device copy (x2.000 and x1.000).  It
-# holds for the kernel source with this sha256 only; otherwise it is reported
-# as null.
-TRAFFIC_KERNEL_SHA256 = "2a2900027faad2a8e829bb0f88fb312ec67ef234c10b706d8fa3bf0e01685190"
-TRAFFIC_SPLITS = 16
-TRAFFIC_BYTES_PER_LAUNCH = 9.62e6
-# Counters of the same profile (rocprofv3 --pmc, per dispatch of k_sweep<2,false>):
-# VALU lane instructions per entry (SQ_INSTS_VALU x 64 / entries), v_exp_f32 per
-# entry (SQ_INSTS_VALU_TRANS_F32 x 64 / entries), VALU issue utilisation
-# (lane instructions / duration / (256 x 64 x 2.4 GHz)) and rocprof's VALUBusy.
-PROFILE_COUNTERS = {"valu_instr_per_entry": 5.67, "exp_per_entry": 1.000, "valu_issue_frac": 0.738,
-                    "VALUBusy": 75.6, "source": "profiles/k_sweep_grid128x128.md"}
+# HBM traffic of one k_sweep<2,0> launch on the 128x128 grids (32 splits per
+# direction), averaged over the profiled replay of the default run (k = 150 ...
+# 1149): rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by
+# what the counter reads for a 256 MiB device copy (x2.000 and x1.000).  It
+# holds for the kernel source with this sha256 and that split count only;
+# otherwise it is reported as null.
+TRAFFIC_KERNEL_SHA256 = "521e0cf5d468901ba42bdb394675c47fbc491b3853d4e081e3b86e972cb06805"
+TRAFFIC_SPLITS = 32
+TRAFFIC_BYTES_PER_LAUNCH = 14.68e6
+# Counters of the same profile (per dispatch of k_sweep<2,0> in the replay):
+# VALU lane instructions and v_exp_f32 per evaluated entry (x 64 / evaluated
+# entries), VALU issue utilisation (lane instructions / duration / (256 x 64 x
+# 2.4 GHz)) and rocprof's VALUBusy.
+PROFILE_COUNTERS = {"valu_instr_per_evaluated_entry": 11.94, "exp_per_evaluated_entry": 1.000,
+                    "valu_issue_frac": 0.307, "VALUBusy": 22.7,
+                    "source": "profiles/k_sweep_grid128x128.md"}
 
 
 def profiled_counters(splits_row: int):

@@ -311,6 +311,8 @@ void fill_ctx(bdrs_solver s) {
   c.plan_stats = (double*)(base + L.plan_stats);
   c.tile_count = nullptr;  // set for profiled sweeps only
   c.tile_total = nullptr;
+  c.ev_start = nullptr;
+  c.ev_stop = nullptr;
 }
 
 // reads the device iteration counter (synchronises the stream)
@@ -352,10 +354,10 @@ hipError_t sweep(bdrs_solver s, bool transpose, bool cert, int splits, double ep
   LaunchCtx c = s->ctx;
   c.tile_count = (unsigned*)(base + s->L.tile_count);
   c.tile_total = (unsigned long long*)(base + s->L.tile_total);
-  hipEvent_t a = s->ev_pool[s->ev_used], b = s->ev_pool[s->ev_used + 1];
-  hipError_t e = hipEventRecord(a, c.stream);
-  if (e == hipSuccess) e = launch_sweep(c, transpose, cert, splits, eps_arg, kofs);
-  if (e == hipSuccess) e = hipEventRecord(b, c.stream);
+  // the launch records the events at the kernel's own start and end
+  c.ev_start = s->ev_pool[s->ev_used];
+  c.ev_stop = s->ev_pool[s->ev_used + 1];
+  hipError_t e = launch_sweep(c, transpose, cert, splits, eps_arg, kofs);
   const int np_out = transpose ? c.cols.np : c.rows.np;
   if (e == hipSuccess) e = launch_count_tiles(c, splits * (np_out / kTile));
   if (e == hipSuccess) {

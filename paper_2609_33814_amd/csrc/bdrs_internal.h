@@ -149,6 +149,9 @@ struct LaunchCtx {
   // the number of input tiles it evaluated, and their running total
   unsigned* tile_count;
   unsigned long long* tile_total;
+  // profiling only (null otherwise): events the sweep launch itself records at
+  // the start and the end of the kernel (not around its dispatch)
+  hipEvent_t ev_start, ev_stop;
 };
 
 // One work item of a batched phase: problem index into the descriptor array,

@@ -34,6 +34,8 @@
 // sweep's weights) or of Algorithm 2 (column mean costs and masses).
 #include "bdrs_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <math.h>
 
 namespace bdrs {
@@ -1217,10 +1219,17 @@ hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int split
   const SideDev& in = transpose ? c.rows : c.cols;
   const int tps = (in.ntiles + splits - 1) / splits;
   dim3 grid(out.np / kSweepBlock, splits);
-#define BDRS_SWEEP(DD, CC)                                                                          \
-  hipLaunchKernelGGL((k_sweep<DD, CC>), grid, dim3(kSweepBlock), 0, c.stream, out.abs, out.np, in.off,  \
-                     in.A, in.tile, in.ntiles, in.count, tps, out.hint,                                  \
-                     c.part.rec, c.ctrl, eps_arg, kofs, transpose ? 0 : 1, c.tile_count)
+#define BDRS_SWEEP(DD, CC)                                                                             \
+  if (c.ev_start && c.ev_stop)                                                                         \
+    hipExtLaunchKernelGGL((k_sweep<DD, CC>), grid, dim3(kSweepBlock), 0, c.stream, c.ev_start, c.ev_stop, \
+                          0u, (const float*)out.abs, (int)out.np, (const float*)in.off,                 \
+                          (const float*)in.A, (const TileRec*)in.tile, (int)in.ntiles, (int)in.count,   \
+                          (int)tps, (const int*)out.hint, (PartialRec*)c.part.rec, (const Ctrl*)c.ctrl, \
+                          (double)eps_arg, (int)kofs, (int)(transpose ? 0 : 1), (unsigned*)c.tile_count);  \
+  else                                                                                                 \
+    hipLaunchKernelGGL((k_sweep<DD, CC>), grid, dim3(kSweepBlock), 0, c.stream, out.abs, out.np, in.off, \
+                       in.A, in.tile, in.ntiles, in.count, tps, out.hint,                               \
+                       c.part.rec, c.ctrl, eps_arg, kofs, transpose ? 0 : 1, c.tile_count)
   switch (c.dim * 2 + (cert ? 1 : 0)) {
     case 2: BDRS_SWEEP(1, kSweepPlain); break;
     case 3: BDRS_SWEEP(1, kSweepCert); break;
