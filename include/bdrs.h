@@ -359,7 +359,7 @@ BDRS_API bdrs_status bdrs_server_destroy(bdrs_server s);
 
 /*
  * Tile-shape autotuner.  The work tile of one sweep launch is a block of
- * outputs (512 outputs, 8 wavefronts of 64) against one "split" of the input
+ * outputs (256 outputs, 4 wavefronts of 64) against one "split" of the input
  * tiles; the number of splits per sweep direction decides how many tiles one
  * work item streams, how many partial (max, sum) records the epilogue merges
  * and how many work items fill the 256 CUs.  A process-wide table keyed by

@@ -11,7 +11,7 @@ constexpr int kBlock = 256;       // threads per block of the O(n) kernels
 // threads per sweep block: the waves of one block share the input tiles of
 // their split (read once through the scalar cache for all of them)
 #ifndef BDRS_SWEEP_BLOCK
-#define BDRS_SWEEP_BLOCK 512
+#define BDRS_SWEEP_BLOCK 256
 #endif
 constexpr int kSweepBlock = BDRS_SWEEP_BLOCK;
 constexpr int kPad = kSweepBlock > kBlock ? kSweepBlock : kBlock;  // np is a multiple of this
