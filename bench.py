@@ -37,21 +37,22 @@ EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters
                      # 64 lane-ops/CU/cycle ceiling, which a 2-slot exp would put above 100%
 
 
-# HBM traffic of one k_sweep<2,0> launch on the 128x128 grids (32 splits per
+# HBM traffic of one k_sweep<2,0> launch on the 128x128 grids (16 splits per
 # direction), averaged over the profiled replay of the default run (k = 150 ...
 # 1149): rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by
 # what the counter reads for a 256 MiB device copy (x2.000 and x1.000).  It
-# holds for the kernel source with this sha256 and that split count only;
-# otherwise it is reported as null.
-TRAFFIC_KERNEL_SHA256 = "521e0cf5d468901ba42bdb394675c47fbc491b3853d4e081e3b86e972cb06805"
-TRAFFIC_SPLITS = 32
-TRAFFIC_BYTES_PER_LAUNCH = 14.68e6
+# holds for the kernel sources with this sha256 (of bdrs_kernels.hip followed
+# by bdrs_internal.h) and that split count only; otherwise it is reported as
+# null.
+TRAFFIC_KERNEL_SHA256 = "947487dcd600791d5a953ee5a71ff6a9e89377b410cfc490fd7dd5eea3dcabdb"
+TRAFFIC_SPLITS = 16
+TRAFFIC_BYTES_PER_LAUNCH = 8.55e6
 # Counters of the same profile (per dispatch of k_sweep<2,0> in the replay):
 # VALU lane instructions and v_exp_f32 per evaluated entry (x 64 / evaluated
 # entries), VALU issue utilisation (lane instructions / duration / (256 x 64 x
 # 2.4 GHz)) and rocprof's VALUBusy.
-PROFILE_COUNTERS = {"valu_instr_per_evaluated_entry": 11.94, "exp_per_evaluated_entry": 1.000,
-                    "valu_issue_frac": 0.307, "VALUBusy": 22.7,
+PROFILE_COUNTERS = {"valu_instr_per_evaluated_entry": 10.92, "exp_per_evaluated_entry": 1.000,
+                    "valu_issue_frac": 0.275, "VALUBusy": 20.0,
                     "source": "profiles/k_sweep_grid128x128.md"}
 
 
@@ -61,11 +62,13 @@ def profiled_counters(splits_row: int):
 
 def measured_traffic(splits_row: int):
     import hashlib
-    src = os.path.join(ROOT, "paper_2609_33814_amd", "csrc", "bdrs_kernels.hip")
+    m = hashlib.sha256()
     try:
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        for name in ("bdrs_kernels.hip", "bdrs_internal.h"):
+            m.update(open(os.path.join(ROOT, "paper_2609_33814_amd", "csrc", name), "rb").read())
     except OSError:
         return None
+    sha = m.hexdigest()
     if sha != TRAFFIC_KERNEL_SHA256 or splits_row != TRAFFIC_SPLITS:
         return None
     return TRAFFIC_BYTES_PER_LAUNCH
