@@ -251,11 +251,6 @@ __device__ __forceinline__ void sweep_block(
     gfloat* __restrict__ a_t = in_A + (size_t)t * kTile + lane0;
     gfloat* __restrict__ offs_n = in_off + (size_t)tn * D * kTile;
     gfloat* __restrict__ a_n = in_A + (size_t)tn * kTile + lane0;
-    if (__double_as_longlong(cur.amax) == (long long)0xFFF0000000000000ULL) {  // -inf: no mass
-      cur = load_tile<D>(in_tile + tn);
-      grp = load_group<D>(offs_n, a_n, 0);
-      continue;
-    }
     float a[D], B[D], na = 0.0f;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -278,8 +273,12 @@ __device__ __forceinline__ void sweep_block(
     }
     const double ub = cur.alpha + (double)ubf;
     // every term of this tile lies below 2^-64 of the running maximum on every
-    // lane: the tile cannot change any sum in float32, so it is skipped
-    if (__all(ub < Mlo)) {
+    // lane: the tile cannot change any sum in float32, so it is skipped.  A
+    // tile without mass (alpha = -inf) is skipped here once M is finite, and
+    // by its maximum below; testing the maximum first would make every tile
+    // wait for two scalar round trips (the maximum, then the bound's fields)
+    if (__all(ub < Mlo) ||
+        __double_as_longlong(cur.amax) == (long long)0xFFF0000000000000ULL) {  // -inf: no mass
       cur = load_tile<D>(in_tile + tn);
       grp = load_group<D>(offs_n, a_n, 0);
       continue;
