@@ -242,129 +242,168 @@ __device__ __forceinline__ void sweep_block(
   // the address), which leaves the scalar path to the offsets and tile
   // records: moving either kind the other way measured slower.
   const int lane0 = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
-  TileVals<D> cur = load_tile<D>(in_tile + t0);
-  Group<D> grp = load_group<D>(in_off + (size_t)t0 * D * kTile, in_A + (size_t)t0 * kTile + lane0, 0);
-  for (int t = t0; t < t1; ++t) {
-    const int tn = min(t + 1, t1 - 1);         // next tile (the last one re-reads itself)
-    // tile addresses computed before any lane-dependent branch
-    gfloat* __restrict__ offs_t = in_off + (size_t)t * D * kTile;
-    gfloat* __restrict__ a_t = in_A + (size_t)t * kTile + lane0;
-    gfloat* __restrict__ offs_n = in_off + (size_t)tn * D * kTile;
-    gfloat* __restrict__ a_n = in_A + (size_t)tn * kTile + lane0;
-    float a[D], B[D], na = 0.0f;
+  const int lane = (int)(threadIdx.x & (kTile - 1));
+  // the wavefront's output box (all lanes, padding included: a larger box
+  // only loosens the coarse bound below)
+  float blo[D], bhi[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      a[d] = P[d] - cur.ctr[d];
-      na = fmaf(a[d], a[d], na);
-      B[d] = kap2x2 * a[d];
-    }
-    const double base = cur.amax - kap2d * (double)na;  // Amax_t - kappa2 |a|^2
-    // upper bound of the exponents w2_q - kappa2 |a - b_q|^2 of this tile:
-    // w2_q <= alpha + gamma . b_q + rho, and the concave quadratic
-    // gamma . b - kappa2 |a - b|^2 is maximised over the tile's box per axis
-    float ubf = cur.rho;
+  for (int d = 0; d < D; ++d) {
+    blo[d] = (float)(-wave_max(-(double)P[d]));
+    bhi[d] = (float)wave_max((double)P[d]);
+  }
+  Group<D> grp;
+  for (int c0 = t0; c0 < t1; c0 += kTile) {
+    const int c1 = min(c0 + kTile, t1);
+    // Coarse test of up to 64 tiles at once, lane l taking tile c0 + l: an
+    // upper bound of the exponents of the tile's points for every output of
+    // the wavefront, alpha + sum_d |gamma_d| r_d + rho - kappa2 dist^2(output
+    // box, tile box), against the smallest running maximum of the wavefront.
+    // It bounds each lane's own bound from above, so a tile it rejects would be
+    // skipped by the per-lane test too; the others are tested per lane below.
+    unsigned long long cand;
+    {
+      const double mlo_min = -wave_max(-Mlo);
+      gtile* rec = in_tile + min(c0 + lane, c1 - 1);
+      gfloat* fp = (gfloat*)rec;
+      const double alpha = ((gdouble*)rec)[1];
+      float w = fp[13], g2 = 0.0f;
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const float g = cur.gam[d], rad = cur.rad[d];
-      const float bs = __builtin_amdgcn_fmed3f(fmaf(g, inv2kap, a[d]), -rad, rad);  // clamp to the box
-      const float df = a[d] - bs;
-      ubf = fmaf(g, bs, ubf);
-      ubf = fmaf(-kap2f, df * df, ubf);
+      for (int d = 0; d < D; ++d) {
+        const float ctr = fp[4 + d], rad = fp[7 + d], gam = fp[10 + d];
+        w = fmaf(fabsf(gam), rad, w);
+        // gap between the boxes, shrunk by a relative 1e-5 against rounding
+        const float gap = fmaxf(0.0f, fmaxf((ctr - rad) - bhi[d], blo[d] - (ctr + rad))) * 0.99999f;
+        g2 = fmaf(gap, gap, g2);
+      }
+      const double cub = alpha + (double)fmaf(-kap2f, g2, w);
+      cand = __ballot(c0 + lane < c1 && !(cub < mlo_min));
     }
-    const double ub = cur.alpha + (double)ubf;
-    // every term of this tile lies below 2^-64 of the running maximum on every
-    // lane: the tile cannot change any sum in float32, so it is skipped.  A
-    // tile without mass (alpha = -inf) is skipped here once M is finite, and
-    // by its maximum below; testing the maximum first would make every tile
-    // wait for two scalar round trips (the maximum, then the bound's fields)
-    if (__all(ub < Mlo) ||
-        __double_as_longlong(cur.amax) == (long long)0xFFF0000000000000ULL) {  // -inf: no mass
-      cur = load_tile<D>(in_tile + tn);
-      grp = load_group<D>(offs_n, a_n, 0);
-      continue;
+    if (cand) {
+      const int tf = c0 + __builtin_ctzll(cand);
+      grp = load_group<D>(in_off + (size_t)tf * D * kTile, in_A + (size_t)tf * kTile + lane0, 0);
     }
-    ++evaluated;
+    while (cand) {
+      const int t = c0 + __builtin_ctzll(cand);
+      cand &= cand - 1;
+      const TileVals<D> cur = load_tile<D>(in_tile + t);
+      const int tn = cand ? c0 + __builtin_ctzll(cand) : t;  // next candidate (the last re-reads itself)
+      // tile addresses computed before any lane-dependent branch
+      gfloat* __restrict__ offs_t = in_off + (size_t)t * D * kTile;
+      gfloat* __restrict__ a_t = in_A + (size_t)t * kTile + lane0;
+      gfloat* __restrict__ offs_n = in_off + (size_t)tn * D * kTile;
+      gfloat* __restrict__ a_n = in_A + (size_t)tn * kTile + lane0;
+      float a[D], B[D], na = 0.0f;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        a[d] = P[d] - cur.ctr[d];
+        na = fmaf(a[d], a[d], na);
+        B[d] = kap2x2 * a[d];
+      }
+      const double base = cur.amax - kap2d * (double)na;  // Amax_t - kappa2 |a|^2
+      // upper bound of the exponents w2_q - kappa2 |a - b_q|^2 of this tile:
+      // w2_q <= alpha + gamma . b_q + rho, and the concave quadratic
+      // gamma . b - kappa2 |a - b|^2 is maximised over the tile's box per axis
+      float ubf = cur.rho;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const float g = cur.gam[d], rad = cur.rad[d];
+        const float bs = __builtin_amdgcn_fmed3f(fmaf(g, inv2kap, a[d]), -rad, rad);  // clamp to the box
+        const float df = a[d] - bs;
+        ubf = fmaf(g, bs, ubf);
+        ubf = fmaf(-kap2f, df * df, ubf);
+      }
+      const double ub = cur.alpha + (double)ubf;
+      // every term of this tile lies below 2^-64 of the running maximum on every
+      // lane: the tile cannot change any sum in float32, so it is skipped.  A
+      // tile without mass (alpha = -inf) is skipped here once M is finite, and
+      // by its maximum below; testing the maximum first would make every tile
+      // wait for two scalar round trips (the maximum, then the bound's fields)
+      if (__all(ub < Mlo) ||
+          __double_as_longlong(cur.amax) == (long long)0xFFF0000000000000ULL) {  // -inf: no mass
+        grp = load_group<D>(offs_n, a_n, 0);
+        continue;
+      }
+      ++evaluated;
 
-    if (ub > Mth) {
-      // exact maximum of this tile for the lanes whose bound exceeds the window
-      gfloat* __restrict__ offs = offs_t;
-      gfloat* __restrict__ Aq = a_t;
-      float tm = -INFINITY;
-      int qi = 0;
+      if (ub > Mth) {
+        // exact maximum of this tile for the lanes whose bound exceeds the window
+        gfloat* __restrict__ offs = offs_t;
+        gfloat* __restrict__ Aq = a_t;
+        float tm = -INFINITY;
+        int qi = 0;
 #pragma unroll 8
-      for (int q = 0; q < kTile; ++q) {
-        float z = Aq[q];
+        for (int q = 0; q < kTile; ++q) {
+          float z = Aq[q];
 #pragma unroll
-        for (int d = 0; d < D; ++d) z = fmaf(B[d], offs[d * kTile + q], z);
-        if (z > tm) {
-          tm = z;
-          qi = q;
-        }
-      }
-      const double tmd = base + (double)tm;
-      if (tmd > M) {
-        const float sc = fast_exp2((float)(M - tmd));
-        S *= sc;
-        if (CERT) N *= sc;
-        if (BARY) {
-#pragma unroll
-          for (int d = 0; d < D; ++d) V[d] *= sc;
-        }
-        M = tmd;
-        Mth = M + kThresh;
-        Mlo = M - kThresh;
-        J = t * kTile + qi;
-      }
-    }
-    const float cm = (float)(base - M);
-    const TileVals<D> nxt = load_tile<D>(in_tile + tn);
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-    float n0 = 0.f, n1 = 0.f;
-    float vt[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) vt[d] = 0.0f;
-#pragma unroll
-    for (int g = 0; g < kTile / kGroup; ++g) {
-      // request the next group (the first group of the next tile after the last)
-      const Group<D> nx = (g + 1 < kTile / kGroup) ? load_group<D>(offs_t, a_t, g + 1)
-                                                  : load_group<D>(offs_n, a_n, 0);
-#pragma unroll
-      for (int u = 0; u < kGroup; ++u) {
-        float z = cm;
-#pragma unroll
-        for (int d = 0; d < D; ++d) z = fmaf(B[d], grp.b[d][u], z);
-        z += grp.a[u];
-        const float e = fast_exp2(z);
-        if (g == 0 && u < 4) {
-          (u == 0 ? s0 : u == 1 ? s1 : u == 2 ? s2 : s3) = e;
-        } else {
-          (u % 4 == 0 ? s0 : u % 4 == 1 ? s1 : u % 4 == 2 ? s2 : s3) += e;
-        }
-        if (CERT) {
-          float c2 = 0.0f;
-#pragma unroll
-          for (int d = 0; d < D; ++d) {
-            const float df = a[d] - grp.b[d][u];
-            c2 = fmaf(df, df, c2);
+          for (int d = 0; d < D; ++d) z = fmaf(B[d], offs[d * kTile + q], z);
+          if (z > tm) {
+            tm = z;
+            qi = q;
           }
-          if (u & 1) n1 = fmaf(c2, e, n1); else n0 = fmaf(c2, e, n0);
         }
-        if (BARY) {
+        const double tmd = base + (double)tm;
+        if (tmd > M) {
+          const float sc = fast_exp2((float)(M - tmd));
+          S *= sc;
+          if (CERT) N *= sc;
+          if (BARY) {
 #pragma unroll
-          for (int d = 0; d < D; ++d) vt[d] = fmaf(e, grp.b[d][u], vt[d]);
+            for (int d = 0; d < D; ++d) V[d] *= sc;
+          }
+          M = tmd;
+          Mth = M + kThresh;
+          Mlo = M - kThresh;
+          J = t * kTile + qi;
         }
       }
-      grp = nx;
-    }
-    const float st = (s0 + s1) + (s2 + s3);
-    S += st;
-    if (CERT) N += n0 + n1;
-    if (BARY) {
-      // sum_q e_q y_q = c_t sum_q e_q + sum_q e_q b_q (points = tile centre + offset)
+      const float cm = (float)(base - M);
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+      float n0 = 0.f, n1 = 0.f;
+      float vt[D];
 #pragma unroll
-      for (int d = 0; d < D; ++d) V[d] += fmaf(cur.ctr[d], st, vt[d]);
+      for (int d = 0; d < D; ++d) vt[d] = 0.0f;
+#pragma unroll
+      for (int g = 0; g < kTile / kGroup; ++g) {
+        // request the next group (the first group of the next tile after the last)
+        const Group<D> nx = (g + 1 < kTile / kGroup) ? load_group<D>(offs_t, a_t, g + 1)
+                                                    : load_group<D>(offs_n, a_n, 0);
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+          float z = cm;
+#pragma unroll
+          for (int d = 0; d < D; ++d) z = fmaf(B[d], grp.b[d][u], z);
+          z += grp.a[u];
+          const float e = fast_exp2(z);
+          if (g == 0 && u < 4) {
+            (u == 0 ? s0 : u == 1 ? s1 : u == 2 ? s2 : s3) = e;
+          } else {
+            (u % 4 == 0 ? s0 : u % 4 == 1 ? s1 : u % 4 == 2 ? s2 : s3) += e;
+          }
+          if (CERT) {
+            float c2 = 0.0f;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+              const float df = a[d] - grp.b[d][u];
+              c2 = fmaf(df, df, c2);
+            }
+            if (u & 1) n1 = fmaf(c2, e, n1); else n0 = fmaf(c2, e, n0);
+          }
+          if (BARY) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) vt[d] = fmaf(e, grp.b[d][u], vt[d]);
+          }
+        }
+        grp = nx;
+      }
+      const float st = (s0 + s1) + (s2 + s3);
+      S += st;
+      if (CERT) N += n0 + n1;
+      if (BARY) {
+        // sum_q e_q y_q = c_t sum_q e_q + sum_q e_q b_q (points = tile centre + offset)
+#pragma unroll
+        for (int d = 0; d < D; ++d) V[d] += fmaf(cur.ctr[d], st, vt[d]);
+      }
     }
-    cur = nxt;
   }
   if (tile_count && (threadIdx.x & (kTile - 1)) == 0) tile_count[slot] = (unsigned)evaluated;
   if (BARY) {
