@@ -182,40 +182,79 @@ __device__ __forceinline__ void sweep_block(
   const int p = bx * kSweepBlock + threadIdx.x;
   const int t0 = split * tps;
   const int t1 = min(t0 + tps, ntiles_in);
+  // the output point and its hint first: their loads do not wait for the
+  // temperature, whose control-block reads sit behind branches
+  float P[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) P[d] = out_abs[(size_t)d * np_out + p];
+  const int j_hint = hint[p];
   const double eps = row_sweep ? eps_row_of(ctrl, eps_arg, kofs) : eps_of(ctrl, eps_arg, kofs);
   const double kap2d = kLog2eD * ctrl->scale / eps;
   const float kap2x2 = (float)(2.0 * kap2d);
   const float kap2f = (float)kap2d;
   const float inv2kap = (float)(0.5 / kap2d);
 
-  float P[D];
+  // The wavefront's output box (all lanes, padding included: a larger box
+  // only loosens the coarse bound below) and the coarse bound of the first
+  // chunk of tiles, computed before the warm start so that their loads overlap
+  // its own.
+  const int lane0 = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
+  const int lane = (int)(threadIdx.x & (kTile - 1));
+  float blo[D], bhi[D];
 #pragma unroll
-  for (int d = 0; d < D; ++d) P[d] = out_abs[(size_t)d * np_out + p];
+  for (int d = 0; d < D; ++d) {
+    blo[d] = (float)(-wave_max(-(double)P[d]));
+    bhi[d] = (float)wave_max((double)P[d]);
+  }
+  // Coarse test of up to 64 tiles at once, lane l taking tile c0 + l: an
+  // upper bound of the exponents of the tile's points for every output of the
+  // wavefront, alpha + sum_d |gamma_d| r_d + rho - kappa2 dist^2(output box,
+  // tile box), to be compared with the smallest running maximum of the
+  // wavefront.  It bounds each lane's own bound from above, so a tile it
+  // rejects would be skipped by the per-lane test too.  The index is clamped
+  // to a valid tile (t1 >= 1 even for an empty split).
+  auto coarse = [&](int c0, int c1) -> double {
+    gtile* rec = in_tile + min(c0 + lane, c1 - 1);
+    gfloat* fp = (gfloat*)rec;
+    const double alpha = ((gdouble*)rec)[1];
+    float w = fp[13], g2 = 0.0f;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const float ctr = fp[4 + d], rad = fp[7 + d], gam = fp[10 + d];
+      w = fmaf(fabsf(gam), rad, w);
+      // gap between the boxes, shrunk by a relative 1e-5 against rounding
+      const float gap = fmaxf(0.0f, fmaxf((ctr - rad) - bhi[d], blo[d] - (ctr + rad))) * 0.99999f;
+      g2 = fmaf(gap, gap, g2);
+    }
+    return alpha + (double)fmaf(-kap2f, g2, w);
+  };
+  double cub = coarse(t0, min(t0 + kTile, t1));
 
   // Warm start: the exact exponent of one remembered input point is a lower
   // bound of the output's maximum over all inputs, so it is a valid shift for
   // every split (a split whose terms all lie far below it adds ~nothing); it
-  // spares the exact-max pass on the first tile of each split.
+  // spares the exact-max pass on the first tile of each split.  Its loads are
+  // issued unconditionally at a clamped, valid index and the result is masked
+  // afterwards: loads under a branch would wait for their data one by one.
   double M = -INFINITY;
   int J = -1;
   {
-    const int j = hint[p];
-    if (j >= 0 && j < count_in) {
-      const int tj = j / kTile, qj = j % kTile;
-      const double am = in_tile[tj].amax;
-      const float aj = in_A[j];
-      if (am > -INFINITY && aj > -INFINITY) {
-        double na = 0.0, ab = 0.0;
+    const int j = j_hint;
+    const int jc = min(max(j, 0), count_in - 1);
+    const int tj = jc / kTile, qj = jc % kTile;
+    const double am = in_tile[tj].amax;
+    const float aj = in_A[jc];
+    double na = 0.0, ab = 0.0;
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-          const double ad = (double)P[d] - (double)in_tile[tj].ctr[d];
-          const double bd = (double)in_off[((size_t)tj * D + d) * kTile + qj];
-          na += ad * ad;
-          ab += ad * bd;
-        }
-        M = am + (double)aj + kap2d * (2.0 * ab - na);
-        J = j;
-      }
+    for (int d = 0; d < D; ++d) {
+      const double ad = (double)P[d] - (double)in_tile[tj].ctr[d];
+      const double bd = (double)in_off[((size_t)tj * D + d) * kTile + qj];
+      na += ad * ad;
+      ab += ad * bd;
+    }
+    if (j >= 0 && j < count_in && am > -INFINITY && aj > -INFINITY) {
+      M = am + (double)aj + kap2d * (2.0 * ab - na);
+      J = j;
     }
   }
   float S = 0.0f, N = 0.0f;
@@ -241,43 +280,12 @@ __device__ __forceinline__ void sweep_block(
   // The weights are read with broadcast vector loads (a lane-dependent zero in
   // the address), which leaves the scalar path to the offsets and tile
   // records: moving either kind the other way measured slower.
-  const int lane0 = (int)__builtin_amdgcn_mbcnt_lo(0u, 0u);
-  const int lane = (int)(threadIdx.x & (kTile - 1));
-  // the wavefront's output box (all lanes, padding included: a larger box
-  // only loosens the coarse bound below)
-  float blo[D], bhi[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) {
-    blo[d] = (float)(-wave_max(-(double)P[d]));
-    bhi[d] = (float)wave_max((double)P[d]);
-  }
   Group<D> grp;
   for (int c0 = t0; c0 < t1; c0 += kTile) {
     const int c1 = min(c0 + kTile, t1);
-    // Coarse test of up to 64 tiles at once, lane l taking tile c0 + l: an
-    // upper bound of the exponents of the tile's points for every output of
-    // the wavefront, alpha + sum_d |gamma_d| r_d + rho - kappa2 dist^2(output
-    // box, tile box), against the smallest running maximum of the wavefront.
-    // It bounds each lane's own bound from above, so a tile it rejects would be
-    // skipped by the per-lane test too; the others are tested per lane below.
-    unsigned long long cand;
-    {
-      const double mlo_min = -wave_max(-Mlo);
-      gtile* rec = in_tile + min(c0 + lane, c1 - 1);
-      gfloat* fp = (gfloat*)rec;
-      const double alpha = ((gdouble*)rec)[1];
-      float w = fp[13], g2 = 0.0f;
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        const float ctr = fp[4 + d], rad = fp[7 + d], gam = fp[10 + d];
-        w = fmaf(fabsf(gam), rad, w);
-        // gap between the boxes, shrunk by a relative 1e-5 against rounding
-        const float gap = fmaxf(0.0f, fmaxf((ctr - rad) - bhi[d], blo[d] - (ctr + rad))) * 0.99999f;
-        g2 = fmaf(gap, gap, g2);
-      }
-      const double cub = alpha + (double)fmaf(-kap2f, g2, w);
-      cand = __ballot(c0 + lane < c1 && !(cub < mlo_min));
-    }
+    if (c0 != t0) cub = coarse(c0, c1);
+    const double mlo_min = -wave_max(-Mlo);
+    unsigned long long cand = __ballot(c0 + lane < c1 && !(cub < mlo_min));
     if (cand) {
       const int tf = c0 + __builtin_ctzll(cand);
       grp = load_group<D>(in_off + (size_t)tf * D * kTile, in_A + (size_t)tf * kTile + lane0, 0);
