@@ -72,6 +72,9 @@ typedef enum {
 #define BDRS_F_OLD_KERNEL 2u
 #define BDRS_F_NO_MOMENTUM 4u
 #define BDRS_F_DEBIASED 8u
+/* bdrs_solve launches every kernel on its own instead of replaying a
+ * captured block of iterations (see bdrs_solve); the results are the same. */
+#define BDRS_F_NO_GRAPH 16u
 
 typedef struct bdrs_solver_* bdrs_solver;
 
@@ -163,7 +166,14 @@ BDRS_API bdrs_status bdrs_certificate(bdrs_solver s, bdrs_cert *out);
  * iteration k with (k + 1) % cert_every == 0 and after the last; the
  * certificate is fused into that iteration's column sweep.  At most
  * max_iters iterations.  *out holds the last certificate.  Returns BDRS_OK
- * when the target is met, BDRS_NOT_CONVERGED at the cap. */
+ * when the target is met, BDRS_NOT_CONVERGED at the cap.
+ * A block of cert_every iterations that starts at a multiple of cert_every
+ * and ends with its certificate is captured once as a hipGraph (on a private
+ * stream of the solver; the kernels read the iteration counter from device
+ * memory, so the graph holds for every such block) and replayed on the
+ * solver's stream; other blocks, solvers with BDRS_F_REPAIR, OLD_KERNEL,
+ * DEBIASED or BDRS_F_NO_GRAPH, and solvers with profiling on launch their
+ * kernels one by one.  Results are bitwise the same either way. */
 BDRS_API bdrs_status bdrs_solve(bdrs_solver s, double tau, int32_t tau_relative,
                        int32_t max_iters, int32_t cert_every, bdrs_cert *out);
 

@@ -20,6 +20,7 @@ OK, NOT_CONVERGED = 0, 1
 E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_NUMERIC = -1, -2, -3, -4, -5
 F_REPAIR = 1
 F_OLD_KERNEL, F_NO_MOMENTUM, F_DEBIASED = 2, 4, 8
+F_NO_GRAPH = 16
 # Row-update variants of the momentum / kernel ablation (lambda = 1).
 VARIANTS = {
     "dual_bdrs": 0,
@@ -224,7 +225,7 @@ class Solver:
     """
 
     def __init__(self, x, y, r, c, cost_scale, eta=1.0, lam=1.0, omega=1.0,
-                 stream=None, repair=False, variant: str = "dual_bdrs"):
+                 stream=None, repair=False, variant: str = "dual_bdrs", graph: bool = True):
         import torch
         self._torch = torch
         m, dim = int(x.shape[0]), int(x.shape[1])
@@ -241,7 +242,8 @@ class Solver:
         self.params = make_params(m, n, dim, _ptr(xx), _ptr(yy), _ptr(rr), _ptr(cc),
                                   float(cost_scale), float(eta), float(lam), float(omega),
                                   self._ws_ptr, self.bytes, int(self._stream.cuda_stream),
-                                  (F_REPAIR if repair else 0) | VARIANTS[variant])
+                                  (F_REPAIR if repair else 0) | VARIANTS[variant] |
+                                  (0 if graph else F_NO_GRAPH))
         h = ctypes.c_void_p()
         check(lib().bdrs_create(ctypes.byref(self.params), ctypes.byref(h)))
         self._h = h

@@ -137,7 +137,7 @@ bdrs_status check_params(const bdrs_params* p, size_t need) {
   if (!(std::isfinite(p->eta) && p->eta > 0)) return fail(BDRS_E_INVALID, "eta must be finite and > 0");
   if (!(p->lambda >= 1.0 && p->lambda < 2.0)) return fail(BDRS_E_INVALID, "lambda must lie in [1, 2)");
   if (!(std::isfinite(p->omega) && p->omega >= 0)) return fail(BDRS_E_INVALID, "omega must be finite and >= 0");
-  const uint32_t known = BDRS_F_REPAIR | BDRS_F_OLD_KERNEL | BDRS_F_NO_MOMENTUM | BDRS_F_DEBIASED;
+  const uint32_t known = BDRS_F_REPAIR | BDRS_F_OLD_KERNEL | BDRS_F_NO_MOMENTUM | BDRS_F_DEBIASED | BDRS_F_NO_GRAPH;
   if (p->flags & ~known) return fail(BDRS_E_INVALID, "unknown flags 0x%x", p->flags);
   const uint32_t variant = p->flags & (BDRS_F_OLD_KERNEL | BDRS_F_NO_MOMENTUM | BDRS_F_DEBIASED);
   if (variant && p->lambda != 1.0) return fail(BDRS_E_INVALID, "the ablation variant flags need lambda = 1");
@@ -876,6 +876,44 @@ bdrs_status bdrs_certificate(bdrs_solver s, bdrs_cert* out) {
   return read_cert(s, repair, out);
 }
 
+// One block of L iterations of Algorithm 1 ending with the fused certificate,
+// the counter advance and the certificate reductions, captured once on a
+// private stream and replayed on the solver's stream (every kernel reads the
+// iteration counter from device memory, so one graph holds for all blocks).
+bdrs_status launch_block_graph(bdrs_solver s, int L) {
+  if (!s->blk_exec || s->blk_len != L) {
+    if (s->blk_exec) {
+      hipGraphExecDestroy(s->blk_exec);
+      s->blk_exec = nullptr;
+      s->blk_len = 0;
+    }
+    if (!s->cap_stream) HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    const hipStream_t user = s->ctx.stream;
+    s->ctx.stream = s->cap_stream;
+    hipGraph_t g = nullptr;
+    bdrs_status st = BDRS_OK;
+    hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (int i = 0; i < L && st == BDRS_OK; ++i) st = enqueue_iteration(s, i == L - 1, i);
+      if (st == BDRS_OK) e = launch_advance(s->ctx.ctrl, L, s->ctx.stream);
+      if (st == BDRS_OK && e == hipSuccess) e = launch_cert_reduce(s->ctx);
+      const hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
+      if (e == hipSuccess) e = e2;
+    }
+    s->ctx.stream = user;
+    if (e == hipSuccess && st == BDRS_OK) e = hipGraphInstantiate(&s->blk_exec, g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    if (st != BDRS_OK) return st;
+    if (e != hipSuccess) {
+      s->blk_exec = nullptr;
+      return hip_status(e, "block graph");
+    }
+    s->blk_len = L;
+  }
+  HIPCHK(hipGraphLaunch(s->blk_exec, s->ctx.stream));
+  return BDRS_OK;
+}
+
 bdrs_status bdrs_solve(bdrs_solver s, double tau, int32_t tau_relative, int32_t max_iters, int32_t cert_every,
                        bdrs_cert* out) {
   if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
@@ -887,21 +925,33 @@ bdrs_status bdrs_solve(bdrs_solver s, double tau, int32_t tau_relative, int32_t 
   bool have = false;
   bdrs_status st0 = sync_k(s);
   if (st0 != BDRS_OK) return st0;
+  // the captured block needs the certificate fused into the last iteration
+  // and no host-computed temperature (separate certificate sweep, repair)
+  const bool graphs = !repair && !separate_cert(s) && !(s->prm.flags & BDRS_F_NO_GRAPH) && !s->prof;
   int pending = 0;  // iterations enqueued since the counter was last advanced
-  for (int32_t i = 0; i < max_iters; ++i) {
+  for (int32_t i = 0; i < max_iters;) {
     const long long k = s->k + pending;
-    const bool due = ((k + 1) % cert_every == 0) || (i == max_iters - 1);
-    bdrs_status st = enqueue_iteration(s, due && !separate_cert(s), pending);
-    if (st != BDRS_OK) return st;
-    ++pending;
-    if (!due) continue;
-    hipError_t e;
-    if ((e = launch_advance(s->ctx.ctrl, pending, s->ctx.stream)) != hipSuccess) return hip_status(e, "advance");
-    s->k += pending;
-    pending = 0;
-    if (separate_cert(s) && (st = enqueue_cert_only(s)) != BDRS_OK) return st;
-    if ((e = launch_cert_reduce(s->ctx)) != hipSuccess) return hip_status(e, "cert reduce");
-    if (repair && (st = enqueue_repair(s)) != BDRS_OK) return st;
+    bdrs_status st;
+    if (graphs && pending == 0 && k % cert_every == 0 && max_iters - i >= cert_every) {
+      if ((st = launch_block_graph(s, cert_every)) != BDRS_OK) return st;
+      s->k += cert_every;
+      i += cert_every;
+      s->packed_rows = true;
+    } else {
+      const bool due = ((k + 1) % cert_every == 0) || (i == max_iters - 1);
+      st = enqueue_iteration(s, due && !separate_cert(s), pending);
+      if (st != BDRS_OK) return st;
+      ++pending;
+      ++i;
+      if (!due) continue;
+      hipError_t e;
+      if ((e = launch_advance(s->ctx.ctrl, pending, s->ctx.stream)) != hipSuccess) return hip_status(e, "advance");
+      s->k += pending;
+      pending = 0;
+      if (separate_cert(s) && (st = enqueue_cert_only(s)) != BDRS_OK) return st;
+      if ((e = launch_cert_reduce(s->ctx)) != hipSuccess) return hip_status(e, "cert reduce");
+      if (repair && (st = enqueue_repair(s)) != BDRS_OK) return st;
+    }
     st = read_cert(s, repair, &ce);
     have = true;
     if (st != BDRS_OK) {
@@ -1141,6 +1191,8 @@ bdrs_status bdrs_destroy(bdrs_solver s) {
   if (!s) return BDRS_OK;
   hipError_t e = hipStreamSynchronize(s->ctx.stream);
   for (hipEvent_t ev : s->ev_pool) hipEventDestroy(ev);
+  if (s->blk_exec) hipGraphExecDestroy(s->blk_exec);
+  if (s->cap_stream) hipStreamDestroy(s->cap_stream);
   delete s;
   if (e != hipSuccess) return hip_status(e, "destroy");
   return BDRS_OK;

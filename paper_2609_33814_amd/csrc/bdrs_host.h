@@ -105,4 +105,8 @@ struct bdrs_solver_ {
   size_t ev_used = 0;
   double prof_entries = 0.0;
   long long prof_sweeps = 0;
+  // bdrs_solve: one captured block of blk_len iterations with its certificate
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t blk_exec = nullptr;
+  int blk_len = 0;
 };
