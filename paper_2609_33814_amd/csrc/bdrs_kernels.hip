@@ -174,14 +174,18 @@ template <int D, int MODE>
 __device__ __forceinline__ void sweep_block(
     gfloat* __restrict__ out_abs, int np_out,
     gfloat* __restrict__ in_off, gfloat* __restrict__ in_A, gtile* __restrict__ in_tile,
-    int ntiles_in, int count_in, int tps, const int* __restrict__ hint,
+    int ntiles_in, int count_in, int nsplit, const int* __restrict__ hint,
     PartialRec* __restrict__ part, gctrl* __restrict__ ctrl, double eps_arg, int kofs, int bx, int split,
     bool row_sweep, unsigned* __restrict__ tile_count, int slot) {
   constexpr bool CERT = MODE == kSweepCert;
   constexpr bool BARY = MODE == kSweepBary;
   const int p = bx * kSweepBlock + threadIdx.x;
-  const int t0 = split * tps;
-  const int t1 = min(t0 + tps, ntiles_in);
+  // Split `split` of nsplit takes every nsplit-th input tile (split, split +
+  // nsplit, ...), so that each split samples the whole input cloud: late in a
+  // solve only the tiles near an output block matter, and they spread over
+  // all splits instead of crowding into one wavefront's work.  Local index i
+  // is tile split + i nsplit; nt tiles in all.
+  const int nt = split < ntiles_in ? (ntiles_in - 1 - split) / nsplit + 1 : 0;
   // the output point and its hint first: their loads do not wait for the
   // temperature, whose control-block reads sit behind branches
   float P[D];
@@ -211,10 +215,11 @@ __device__ __forceinline__ void sweep_block(
   // wavefront, alpha + sum_d |gamma_d| r_d + rho - kappa2 dist^2(output box,
   // tile box), to be compared with the smallest running maximum of the
   // wavefront.  It bounds each lane's own bound from above, so a tile it
-  // rejects would be skipped by the per-lane test too.  The index is clamped
-  // to a valid tile (t1 >= 1 even for an empty split).
+  // rejects would be skipped by the per-lane test too.  Local indices c0 ...
+  // c1-1; the tile index is clamped to a valid tile (also for an empty split).
   auto coarse = [&](int c0, int c1) -> double {
-    gtile* rec = in_tile + min(c0 + lane, c1 - 1);
+    const int il = max(min(c0 + lane, c1 - 1), 0);
+    gtile* rec = in_tile + min(split + il * nsplit, ntiles_in - 1);
     gfloat* fp = (gfloat*)rec;
     const double alpha = ((gdouble*)rec)[1];
     float w = fp[13], g2 = 0.0f;
@@ -228,7 +233,7 @@ __device__ __forceinline__ void sweep_block(
     }
     return alpha + (double)fmaf(-kap2f, g2, w);
   };
-  double cub = coarse(t0, min(t0 + kTile, t1));
+  double cub = coarse(0, min(kTile, nt));
 
   // Warm start: the exact exponent of one remembered input point is a lower
   // bound of the output's maximum over all inputs, so it is a valid shift for
@@ -262,7 +267,7 @@ __device__ __forceinline__ void sweep_block(
 #pragma unroll
   for (int d = 0; d < D; ++d) V[d] = 0.0f;
   int evaluated = 0;  // input tiles this wavefront evaluated (the same on every lane)
-  if (t0 >= t1) {
+  if (nt == 0) {
     if (tile_count && (threadIdx.x & (kTile - 1)) == 0) tile_count[slot] = 0;
     if (BARY) {
       PartialBary* pb = reinterpret_cast<PartialBary*>(part) + (size_t)split * np_out + p;
@@ -281,20 +286,20 @@ __device__ __forceinline__ void sweep_block(
   // the address), which leaves the scalar path to the offsets and tile
   // records: moving either kind the other way measured slower.
   Group<D> grp;
-  for (int c0 = t0; c0 < t1; c0 += kTile) {
-    const int c1 = min(c0 + kTile, t1);
-    if (c0 != t0) cub = coarse(c0, c1);
+  for (int c0 = 0; c0 < nt; c0 += kTile) {
+    const int c1 = min(c0 + kTile, nt);
+    if (c0 != 0) cub = coarse(c0, c1);
     const double mlo_min = -wave_max(-Mlo);
     unsigned long long cand = __ballot(c0 + lane < c1 && !(cub < mlo_min));
     if (cand) {
-      const int tf = c0 + __builtin_ctzll(cand);
+      const int tf = split + (c0 + __builtin_ctzll(cand)) * nsplit;
       grp = load_group<D>(in_off + (size_t)tf * D * kTile, in_A + (size_t)tf * kTile + lane0, 0);
     }
     while (cand) {
-      const int t = c0 + __builtin_ctzll(cand);
+      const int t = split + (c0 + __builtin_ctzll(cand)) * nsplit;
       cand &= cand - 1;
       const TileVals<D> cur = load_tile<D>(in_tile + t);
-      const int tn = cand ? c0 + __builtin_ctzll(cand) : t;  // next candidate (the last re-reads itself)
+      const int tn = cand ? split + (c0 + __builtin_ctzll(cand)) * nsplit : t;  // next candidate (the last re-reads itself)
       // tile addresses computed before any lane-dependent branch
       gfloat* __restrict__ offs_t = in_off + (size_t)t * D * kTile;
       gfloat* __restrict__ a_t = in_A + (size_t)t * kTile + lane0;
@@ -434,12 +439,12 @@ template <int D, int MODE>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(
     const float* __restrict__ out_abs, int np_out,
     const float* __restrict__ in_off, const float* __restrict__ in_A, const TileRec* __restrict__ in_tile,
-    int ntiles_in, int count_in, int tps, const int* __restrict__ hint,
+    int ntiles_in, int count_in, int nsplit, const int* __restrict__ hint,
     PartialRec* __restrict__ part, const Ctrl* __restrict__ ctrl, double eps_arg, int kofs, int row_sweep,
     unsigned* __restrict__ tile_count) {
   const int slot = (blockIdx.y * gridDim.x + blockIdx.x) * (kSweepBlock / kTile) + threadIdx.x / kTile;
   sweep_block<D, MODE>((gfloat*)out_abs, np_out, (gfloat*)in_off, (gfloat*)in_A, (gtile*)in_tile, ntiles_in,
-                       count_in, tps, hint, part, (gctrl*)ctrl, eps_arg, kofs, blockIdx.x, blockIdx.y,
+                       count_in, nsplit, hint, part, (gctrl*)ctrl, eps_arg, kofs, blockIdx.x, blockIdx.y,
                        row_sweep != 0, tile_count, slot);
 }
 
@@ -455,9 +460,8 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep_batch(const BatchItem* __
   const SideDev& out = transpose ? c.cols : c.rows;
   const SideDev& in = transpose ? c.rows : c.cols;
   const int splits = transpose ? c.splits_col : c.splits_row;
-  const int tps = (in.ntiles + splits - 1) / splits;
   sweep_block<D, MODE>((gfloat*)out.abs, out.np, (gfloat*)in.off, (gfloat*)in.A, (gtile*)in.tile, in.ntiles,
-                       in.count, tps, out.hint, c.part.rec, (gctrl*)c.ctrl, -1.0, kofs, it.blk, it.split,
+                       in.count, splits, out.hint, c.part.rec, (gctrl*)c.ctrl, -1.0, kofs, it.blk, it.split,
                        transpose == 0, nullptr, 0);
 }
 
@@ -1263,18 +1267,17 @@ int choose_splits(int np_out, int ntiles_in) {
 hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int splits, double eps_arg, int kofs) {
   const SideDev& out = transpose ? c.cols : c.rows;
   const SideDev& in = transpose ? c.rows : c.cols;
-  const int tps = (in.ntiles + splits - 1) / splits;
   dim3 grid(out.np / kSweepBlock, splits);
 #define BDRS_SWEEP(DD, CC)                                                                             \
   if (c.ev_start && c.ev_stop)                                                                         \
     hipExtLaunchKernelGGL((k_sweep<DD, CC>), grid, dim3(kSweepBlock), 0, c.stream, c.ev_start, c.ev_stop, \
                           0u, (const float*)out.abs, (int)out.np, (const float*)in.off,                 \
                           (const float*)in.A, (const TileRec*)in.tile, (int)in.ntiles, (int)in.count,   \
-                          (int)tps, (const int*)out.hint, (PartialRec*)c.part.rec, (const Ctrl*)c.ctrl, \
+                          (int)splits, (const int*)out.hint, (PartialRec*)c.part.rec, (const Ctrl*)c.ctrl, \
                           (double)eps_arg, (int)kofs, (int)(transpose ? 0 : 1), (unsigned*)c.tile_count);  \
   else                                                                                                 \
     hipLaunchKernelGGL((k_sweep<DD, CC>), grid, dim3(kSweepBlock), 0, c.stream, out.abs, out.np, in.off, \
-                       in.A, in.tile, in.ntiles, in.count, tps, out.hint,                               \
+                       in.A, in.tile, in.ntiles, in.count, splits, out.hint,                               \
                        c.part.rec, c.ctrl, eps_arg, kofs, transpose ? 0 : 1, c.tile_count)
   switch (c.dim * 2 + (cert ? 1 : 0)) {
     case 2: BDRS_SWEEP(1, kSweepPlain); break;
@@ -1292,11 +1295,10 @@ hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int split
 hipError_t launch_sweep_bary(const LaunchCtx& c, int splits, double eps) {
   const SideDev& out = c.rows;
   const SideDev& in = c.cols;
-  const int tps = (in.ntiles + splits - 1) / splits;
   dim3 grid(out.np / kSweepBlock, splits);
 #define BDRS_SWEEP(DD)                                                                                  \
   hipLaunchKernelGGL((k_sweep<DD, kSweepBary>), grid, dim3(kSweepBlock), 0, c.stream, out.abs, out.np,   \
-                     in.off, in.A, in.tile, in.ntiles, in.count, tps, out.hint, c.part.rec, c.ctrl, eps, 0, 1,    \
+                     in.off, in.A, in.tile, in.ntiles, in.count, splits, out.hint, c.part.rec, c.ctrl, eps, 0, 1,    \
                      c.tile_count)
   switch (c.dim) {
     case 1: BDRS_SWEEP(1); break;
