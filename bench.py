@@ -44,15 +44,15 @@ EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters
 # holds for the kernel sources with this sha256 (of bdrs_kernels.hip followed
 # by bdrs_internal.h) and that split count only; otherwise it is reported as
 # null.
-TRAFFIC_KERNEL_SHA256 = "947487dcd600791d5a953ee5a71ff6a9e89377b410cfc490fd7dd5eea3dcabdb"
+TRAFFIC_KERNEL_SHA256 = "f3fa6864398e38013a5af4418c79107283c1ae37f3e8c1da673b1078c9d22087"
 TRAFFIC_SPLITS = 16
-TRAFFIC_BYTES_PER_LAUNCH = 8.55e6
+TRAFFIC_BYTES_PER_LAUNCH = 6.84e6
 # Counters of the same profile (per dispatch of k_sweep<2,0> in the replay):
 # VALU lane instructions and v_exp_f32 per evaluated entry (x 64 / evaluated
 # entries), VALU issue utilisation (lane instructions / duration / (256 x 64 x
 # 2.4 GHz)) and rocprof's VALUBusy.
-PROFILE_COUNTERS = {"valu_instr_per_evaluated_entry": 10.92, "exp_per_evaluated_entry": 1.000,
-                    "valu_issue_frac": 0.275, "VALUBusy": 20.0,
+PROFILE_COUNTERS = {"valu_instr_per_evaluated_entry": 8.19, "exp_per_evaluated_entry": 1.000,
+                    "valu_issue_frac": 0.283, "VALUBusy": 19.9,
                     "source": "profiles/k_sweep_grid128x128.md"}
 
 
