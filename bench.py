@@ -44,7 +44,7 @@ EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters
 # holds for the kernel sources with this sha256 (of bdrs_kernels.hip followed
 # by bdrs_internal.h) and that split count only; otherwise it is reported as
 # null.
-TRAFFIC_KERNEL_SHA256 = "f3fa6864398e38013a5af4418c79107283c1ae37f3e8c1da673b1078c9d22087"
+TRAFFIC_KERNEL_SHA256 = "510f5aaa50e51617cc37f01fbc72381db3942c52ac6d7944524884e12738c08a"
 TRAFFIC_SPLITS = 16
 TRAFFIC_BYTES_PER_LAUNCH = 6.84e6
 # Counters of the same profile (per dispatch of k_sweep<2,0> in the replay):

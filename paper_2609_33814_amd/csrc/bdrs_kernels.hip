@@ -164,12 +164,15 @@ __device__ __forceinline__ Group<D> load_group(gfloat* __restrict__ offs_t, gflo
   return r;
 }
 
-// One block of kSweepBlock outputs (bx) against one split of the input tiles.
-// The input side is streamed as tiles of 64 points; per tile the lane
-// evaluates z_q = cm + B . b_q + A'_q and accumulates exp2(z_q) (and, for the
-// certificate, the cost-weighted sum).  The next tile's record and the next
-// group of points are requested before the current group is computed, so the
-// scalar loads overlap the arithmetic.
+// One block of kSweepBlock outputs (bx) against one split of the input tiles
+// (every nsplit-th tile).  Per chunk of up to 64 tiles a coarse test against
+// the wavefront's output box picks the candidate tiles; per candidate the lane
+// bounds its own exponents and the wavefront skips the tile when no lane can
+// see it, else every lane evaluates z_q = cm + B . b_q + A'_q and accumulates
+// exp2(z_q) (and, for the certificate, the cost-weighted sum).  The next group
+// of 8 points (after a tile's last group, the next candidate's first) is
+// requested before the current group is computed, so the loads overlap the
+// arithmetic.
 template <int D, int MODE>
 __device__ __forceinline__ void sweep_block(
     gfloat* __restrict__ out_abs, int np_out,
@@ -283,8 +286,8 @@ __device__ __forceinline__ void sweep_block(
   double Mth = M + kThresh;                     // the exact-max gate, updated with M
   double Mlo = M - kThresh;                     // the skip gate, updated with M
   // The weights are read with broadcast vector loads (a lane-dependent zero in
-  // the address), which leaves the scalar path to the offsets and tile
-  // records: moving either kind the other way measured slower.
+  // the address), which leaves the scalar path to the offsets and the
+  // candidates' tile records: moving either kind the other way measured slower.
   Group<D> grp;
   for (int c0 = 0; c0 < nt; c0 += kTile) {
     const int c1 = min(c0 + kTile, nt);
