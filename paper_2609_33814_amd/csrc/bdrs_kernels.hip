@@ -481,16 +481,32 @@ struct Merged {
 __device__ __forceinline__ Merged merge_splits(const PartialRec* __restrict__ part, int splits, int np,
                                                int p) {
   // The epilogue runs few waves, so its time is the number of memory round
-  // trips: one pass over the split records, G of them requested together in
-  // full batches without conditions (a load under a branch waits for its data
-  // before the next one is issued), the remainder one by one.  Each batch is
-  // merged against the running maximum, which is raised first if the batch
-  // holds a larger one (the running sums are rescaled).
+  // trips: one pass over the split records, G of them requested together.
+  // Past the last split the index is clamped to a valid record and its
+  // maximum gets -inf added (so its weight is 0): every loaded value is used
+  // unconditionally, which keeps the loads together (a load the compiler may
+  // sink under a branch waits for its data before the next one is issued).
+  // Each batch is merged against
+  // the running maximum, which is raised first if the batch holds a larger one
+  // (the running sums are rescaled).
   constexpr int G = 16;
-  const int full = splits - splits % G;
   double mx = -INFINITY, S = 0.0, N = 0.0;
   int J = -1;
-  auto raise = [&](double bm, int bj) {
+  for (int s0 = 0; s0 < splits; s0 += G) {
+    PartialRec q[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      q[g] = part[(size_t)min(s0 + g, splits - 1) * np + p];
+      q[g].M += (s0 + g < splits) ? 0.0 : -INFINITY;
+    }
+    double bm = -INFINITY;
+    int bj = -1;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const bool up = q[g].M > bm;  // the first split holding the batch maximum
+      bj = up ? q[g].J : bj;
+      bm = up ? q[g].M : bm;
+    }
     if (bm > mx) {  // strictly: J stays with the first split holding the maximum
       // shifts of one output differ by little: the weight is a hardware float32 exp2
       const double sc = mx == -INFINITY ? 0.0 : (double)fast_exp2((float)(mx - bm));
@@ -499,33 +515,13 @@ __device__ __forceinline__ Merged merge_splits(const PartialRec* __restrict__ pa
       mx = bm;
       J = bj;
     }
-  };
-  auto add = [&](const PartialRec& q) {
-    const double w = (double)fast_exp2((float)(q.M - mx));  // 0 for an empty split
-    S += w * (double)q.S;
-    N += w * (double)q.N;
-  };
-  for (int s0 = 0; s0 < full; s0 += G) {
-    PartialRec q[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) q[g] = part[(size_t)(s0 + g) * np + p];
-    double bm = -INFINITY;
-    int bj = -1;
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const bool up = q[g].M > bm;
-      bj = up ? q[g].J : bj;
-      bm = up ? q[g].M : bm;
-    }
-    raise(bm, bj);
     if (mx == -INFINITY) continue;  // nothing so far
 #pragma unroll
-    for (int g = 0; g < G; ++g) add(q[g]);
-  }
-  for (int s = full; s < splits; ++s) {
-    const PartialRec q = part[(size_t)s * np + p];
-    raise(q.M, q.J);
-    if (mx > -INFINITY) add(q);
+    for (int g = 0; g < G; ++g) {
+      const double w = (double)fast_exp2((float)(q[g].M - mx));  // 0 for an empty or masked split
+      S += w * (double)q[g].S;
+      N += w * (double)q[g].N;
+    }
   }
   Merged r{-INFINITY, 0.0, 0.0, -1};
   if (mx == -INFINITY) return r;  // empty sum
