@@ -59,28 +59,31 @@ def _solver(prob, graph, lam=1.0):
                        t(prob.c, torch.float64), prob.cost_scale, eta=0.1, lam=lam, graph=graph)
 
 
-@pytest.mark.parametrize("lam", [1.0, 1.5])
-def test_solve_block_graphs_match_eager_solve(lam):
-    """bdrs_solve replays a captured block of cert_every iterations; with the
-    graph switched off it launches every kernel itself.  Both must agree bit
-    for bit: aligned blocks, a first block that starts off the block grid
-    (7 eager steps first) and a last block cut short by max_iters."""
+@pytest.mark.parametrize("lam,every", [(1.0, 50), (1.5, 50), (1.0, 20)])
+def test_solve_block_graphs_match_eager_solve(lam, every):
+    """bdrs_solve replays a captured graph for aligned blocks of cert_every
+    iterations (50 and 20 here); with graphs off it launches every kernel
+    itself.
+    Both must agree bit for bit: aligned blocks, a first block that starts off
+    the block grid (7 eager steps first) and a last block cut short by
+    max_iters."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     prob = inputs.grid_problem(32, 11, 12)
     runs = []
+    cap = 2 * every + 30
     for graph in (True, False):
         sv = _solver(prob, graph, lam)
         sv.step(7)
-        ok1, ce1 = sv.solve(0.0, 130, 50)   # 43 eager, then 50 as a block (graph), then 37 eager
-        ok2, ce2 = sv.solve(0.005, 2000, 50)
+        ok1, ce1 = sv.solve(0.0, cap, every)   # eager to the grid, a block as graphs, eager tail
+        ok2, ce2 = sv.solve(0.005, 2000, every)
         runs.append((ok1, ce1, ok2, ce2, sv.get_state(), sv.get_hints()))
     a, b = runs
     assert a[0] == b[0] and a[2] == b[2]
     for ca, cb in ((a[1], b[1]), (a[3], b[3])):
         for key in ca:   # bitwise: equal, or both NaN (fields a plain solve leaves unset)
             assert ca[key] == cb[key] or (ca[key] != ca[key] and cb[key] != cb[key]), (key, ca, cb)
-    assert a[1]["k"] == 7 + 130 - 1
+    assert a[1]["k"] == 7 + cap - 1
     for key in ("la", "lb", "lb_prev", "lah", "lbh", "lt"):
         assert torch.equal(a[4][key], b[4][key]), key
     assert a[4]["k"] == b[4]["k"]
