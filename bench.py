@@ -44,15 +44,15 @@ EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters
 # holds for the kernel sources with this sha256 (of bdrs_kernels.hip followed
 # by bdrs_internal.h) and that split count only; otherwise it is reported as
 # null.
-TRAFFIC_KERNEL_SHA256 = "510f5aaa50e51617cc37f01fbc72381db3942c52ac6d7944524884e12738c08a"
+TRAFFIC_KERNEL_SHA256 = "39f11321115f81f295a7ed8e878540b922be10809184d1740003fc59704e0c86"
 TRAFFIC_SPLITS = 16
-TRAFFIC_BYTES_PER_LAUNCH = 6.84e6
+TRAFFIC_BYTES_PER_LAUNCH = 6.83e6
 # Counters of the same profile (per dispatch of k_sweep<2,0> in the replay):
 # VALU lane instructions and v_exp_f32 per evaluated entry (x 64 / evaluated
 # entries), VALU issue utilisation (lane instructions / duration / (256 x 64 x
 # 2.4 GHz)) and rocprof's VALUBusy.
 PROFILE_COUNTERS = {"valu_instr_per_evaluated_entry": 8.19, "exp_per_evaluated_entry": 1.000,
-                    "valu_issue_frac": 0.283, "VALUBusy": 19.9,
+                    "valu_issue_frac": 0.288, "VALUBusy": 19.9,
                     "source": "profiles/k_sweep_grid128x128.md"}
 
 
