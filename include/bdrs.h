@@ -75,6 +75,12 @@ typedef enum {
 /* bdrs_solve launches every kernel on its own instead of replaying a
  * captured block of iterations (see bdrs_solve); the results are the same. */
 #define BDRS_F_NO_GRAPH 16u
+/* Retain the dual state with the lowest relative gap (U - L) / U of all
+ * certificates so far (the colour-transfer experiments keep that state for
+ * the barycentric projection); bdrs_restore_best brings it back.  Adds an
+ * O(m + n) region to the workspace (bdrs_workspace_size counts it when the
+ * flag is set).  Not accepted by bdrs_batch_solve and the solve server. */
+#define BDRS_F_KEEP_BEST_STATE 32u
 
 typedef struct bdrs_solver_* bdrs_solver;
 
@@ -429,6 +435,16 @@ BDRS_API bdrs_status bdrs_profile_read(bdrs_solver s, int64_t *sweeps, double *m
  * m n per sweep late in a solve.  Counted per (64 outputs, 64 inputs) pair,
  * padding included.  Synchronises the stream. */
 BDRS_API bdrs_status bdrs_profile_evaluated(bdrs_solver s, double *entries);
+
+/* Makes the state retained under BDRS_F_KEEP_BEST_STATE the current one:
+ * the dual state and warm-start hints after the iteration whose certificate
+ * had the lowest relative gap, and its iteration count (*iters_done, may be
+ * NULL).  Later bdrs_plan / bdrs_round / bdrs_get_state / bdrs_certificate /
+ * bdrs_step act on it; the best-bound records are kept.  The retained state
+ * is that of the solver's whole history (bdrs_set_state does not clear it).
+ * BDRS_E_INVALID without the flag, BDRS_E_STATE before the first
+ * certificate.  Synchronises the stream. */
+BDRS_API bdrs_status bdrs_restore_best(bdrs_solver s, int64_t *iters_done);
 
 /* Destroys the solver object (host memory only; the workspace stays the
  * caller's).  Synchronises the stream.  NULL is accepted. */

@@ -21,6 +21,7 @@ E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_NUMERIC = -1, -2, -3, -4, -5
 F_REPAIR = 1
 F_OLD_KERNEL, F_NO_MOMENTUM, F_DEBIASED = 2, 4, 8
 F_NO_GRAPH = 16
+F_KEEP_BEST_STATE = 32
 # Row-update variants of the momentum / kernel ablation (lambda = 1).
 VARIANTS = {
     "dual_bdrs": 0,
@@ -38,7 +39,7 @@ EXPORTS = [
     "bdrs_server_wait", "bdrs_server_stats", "bdrs_server_now", "bdrs_server_destroy",
     "bdrs_get_hints", "bdrs_set_hints", "bdrs_autotune_workspace_size", "bdrs_autotune",
     "bdrs_tune_set", "bdrs_tune_get", "bdrs_tune_clear", "bdrs_plan", "bdrs_server_set_policy",
-    "bdrs_round", "bdrs_profile_evaluated",
+    "bdrs_round", "bdrs_profile_evaluated", "bdrs_restore_best",
 ]
 
 
@@ -179,6 +180,7 @@ def lib() -> ctypes.CDLL:
         L.bdrs_server_set_policy.argtypes = [vp, ctypes.c_double]
         L.bdrs_round.argtypes = [vp, P(RoundStats)]
         L.bdrs_profile_evaluated.argtypes = [vp, P(ctypes.c_double)]
+        L.bdrs_restore_best.argtypes = [vp, P(ctypes.c_int64)]
         L.bdrs_last_error.restype = ctypes.c_char_p
         L.bdrs_version.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -207,9 +209,9 @@ def make_params(m, n, dim, x=0, y=0, r=0, c=0, cost_scale=1.0, eta=1.0, lam=1.0,
                   workspace_bytes, stream, flags)
 
 
-def workspace_size(m: int, n: int, dim: int) -> int:
+def workspace_size(m: int, n: int, dim: int, flags: int = 0) -> int:
     out = ctypes.c_size_t()
-    p = make_params(m, n, dim)
+    p = make_params(m, n, dim, flags=flags)
     check(lib().bdrs_workspace_size(ctypes.byref(p), ctypes.byref(out)))
     return out.value
 
@@ -225,13 +227,16 @@ class Solver:
     """
 
     def __init__(self, x, y, r, c, cost_scale, eta=1.0, lam=1.0, omega=1.0,
-                 stream=None, repair=False, variant: str = "dual_bdrs", graph: bool = True):
+                 stream=None, repair=False, variant: str = "dual_bdrs", graph: bool = True,
+                 keep_best: bool = False):
         import torch
         self._torch = torch
         m, dim = int(x.shape[0]), int(x.shape[1])
         n = int(y.shape[0])
         self.m, self.n, self.dim = m, n, dim
-        self.bytes = workspace_size(m, n, dim)
+        flags = ((F_REPAIR if repair else 0) | VARIANTS[variant] | (0 if graph else F_NO_GRAPH) |
+                 (F_KEEP_BEST_STATE if keep_best else 0))
+        self.bytes = workspace_size(m, n, dim, flags)
         # 256-byte aligned workspace carved out of a torch allocation
         self._ws = torch.empty(self.bytes + 256, dtype=torch.uint8, device=x.device)
         base = self._ws.data_ptr()
@@ -242,8 +247,7 @@ class Solver:
         self.params = make_params(m, n, dim, _ptr(xx), _ptr(yy), _ptr(rr), _ptr(cc),
                                   float(cost_scale), float(eta), float(lam), float(omega),
                                   self._ws_ptr, self.bytes, int(self._stream.cuda_stream),
-                                  (F_REPAIR if repair else 0) | VARIANTS[variant] |
-                                  (0 if graph else F_NO_GRAPH))
+                                  flags)
         h = ctypes.c_void_p()
         check(lib().bdrs_create(ctypes.byref(self.params), ctypes.byref(h)))
         self._h = h
@@ -265,6 +269,12 @@ class Solver:
         st = check(lib().bdrs_solve(self._h, float(tau), 1 if relative else 0, int(max_iters),
                                     int(cert_every), ctypes.byref(ce)), allow=(OK, NOT_CONVERGED))
         return st == OK, ce.as_dict()
+
+    def restore_best(self) -> int:
+        """Makes the retained lowest-gap state current (keep_best=True); returns its iteration count."""
+        k = ctypes.c_int64()
+        check(lib().bdrs_restore_best(self._h, ctypes.byref(k)))
+        return k.value
 
     def get_state(self) -> dict:
         torch = self._torch

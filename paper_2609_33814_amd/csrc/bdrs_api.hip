@@ -56,8 +56,9 @@ int normalize_splits(int s, int ntiles_in) {
   return (ntiles_in + tps - 1) / tps;
 }
 
-Layout make_layout(int m, int n, int dim, int reserve_row, int reserve_col) {
+Layout make_layout(int m, int n, int dim, int reserve_row, int reserve_col, bool keep_best) {
   Layout L{};
+  L.keep_best = keep_best;
   L.R = side_shape(m);
   L.C = side_shape(n);
   L.splits_row = choose_splits(L.R.np, L.C.ntiles);
@@ -107,6 +108,17 @@ Layout make_layout(int m, int n, int dim, int reserve_row, int reserve_col) {
   L.plan_col = take(sizeof(double) * L.C.np);
   L.plan_stats = take(sizeof(double) * kCertSlots);
   L.tile_total = take(sizeof(unsigned long long));
+  if (keep_best) {
+    L.best_la = take(sizeof(double) * L.R.np);
+    L.best_lah = take(sizeof(double) * L.R.np);
+    L.best_lb1 = take(sizeof(double) * L.C.np);
+    L.best_lb2 = take(sizeof(double) * L.C.np);
+    L.best_lbh = take(sizeof(double) * L.C.np);
+    L.best_lt0 = take(sizeof(double) * L.C.np);
+    L.best_lt1 = take(sizeof(double) * L.C.np);
+    L.best_hr = take(sizeof(int) * L.R.np);
+    L.best_hc = take(sizeof(int) * L.C.np);
+  }
   // partial records last: every other offset is independent of the split counts
   const size_t rows_rec = (size_t)std::max(L.splits_row, reserve_row) * L.R.np;
   const size_t cols_rec = (size_t)std::max(L.splits_col, reserve_col) * L.C.np;
@@ -137,7 +149,8 @@ bdrs_status check_params(const bdrs_params* p, size_t need) {
   if (!(std::isfinite(p->eta) && p->eta > 0)) return fail(BDRS_E_INVALID, "eta must be finite and > 0");
   if (!(p->lambda >= 1.0 && p->lambda < 2.0)) return fail(BDRS_E_INVALID, "lambda must lie in [1, 2)");
   if (!(std::isfinite(p->omega) && p->omega >= 0)) return fail(BDRS_E_INVALID, "omega must be finite and >= 0");
-  const uint32_t known = BDRS_F_REPAIR | BDRS_F_OLD_KERNEL | BDRS_F_NO_MOMENTUM | BDRS_F_DEBIASED | BDRS_F_NO_GRAPH;
+  const uint32_t known = BDRS_F_REPAIR | BDRS_F_OLD_KERNEL | BDRS_F_NO_MOMENTUM | BDRS_F_DEBIASED | BDRS_F_NO_GRAPH |
+                         BDRS_F_KEEP_BEST_STATE;
   if (p->flags & ~known) return fail(BDRS_E_INVALID, "unknown flags 0x%x", p->flags);
   const uint32_t variant = p->flags & (BDRS_F_OLD_KERNEL | BDRS_F_NO_MOMENTUM | BDRS_F_DEBIASED);
   if (variant && p->lambda != 1.0) return fail(BDRS_E_INVALID, "the ablation variant flags need lambda = 1");
@@ -146,7 +159,7 @@ bdrs_status check_params(const bdrs_params* p, size_t need) {
     return fail(BDRS_E_INVALID, "flags: BDRS_F_DEBIASED needs BDRS_F_OLD_KERNEL and BDRS_F_NO_MOMENTUM");
   if (!p->workspace) return fail(BDRS_E_INVALID, "workspace is NULL");
   if (((uintptr_t)p->workspace) % kAlign) return fail(BDRS_E_INVALID, "workspace must be 256-byte aligned");
-  if (need == 0) need = make_layout(p->m, p->n, p->dim).total;
+  if (need == 0) need = make_layout(p->m, p->n, p->dim, 0, 0, (p->flags & BDRS_F_KEEP_BEST_STATE) != 0).total;
   if (p->workspace_bytes < need)
     return fail(BDRS_E_NOMEM, "workspace too small: %zu bytes given, %zu needed", p->workspace_bytes, need);
   return BDRS_OK;
@@ -397,6 +410,30 @@ bdrs_status repack(bdrs_solver s) {
 }
 
 // certificate record (kCertSlots doubles, host) -> bdrs_cert, updating the best bounds
+// Copies the dual state and the hints into the retained-state region
+// (to_best) or back, on the solver's stream (device to device, tile order).
+hipError_t copy_best(bdrs_solver s, bool to_best) {
+  const LaunchCtx& c = s->ctx;
+  char* base = (char*)s->prm.workspace;
+  const size_t nr = sizeof(double) * c.rows.np, nc = sizeof(double) * c.cols.np;
+  struct Pair {
+    void* live;
+    size_t best, bytes;
+  } pairs[] = {
+      {c.st.la, s->L.best_la, nr},   {c.st.lah, s->L.best_lah, nr}, {c.st.lb1, s->L.best_lb1, nc},
+      {c.st.lb2, s->L.best_lb2, nc}, {c.st.lbh, s->L.best_lbh, nc}, {c.st.lt[0], s->L.best_lt0, nc},
+      {c.st.lt[1], s->L.best_lt1, nc}, {c.rows.hint, s->L.best_hr, sizeof(int) * c.rows.np},
+      {c.cols.hint, s->L.best_hc, sizeof(int) * c.cols.np},
+  };
+  hipError_t e = hipSuccess;
+  for (const Pair& q : pairs) {
+    void* b = base + q.best;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(to_best ? b : q.live, to_best ? q.live : b, q.bytes, hipMemcpyDeviceToDevice, c.stream);
+  }
+  return e;
+}
+
 bdrs_status cert_from_record(bdrs_solver s, const double* h, bool repair, bdrs_cert* out) {
   bdrs_cert ce;
   ce.k = (int64_t)h[0];
@@ -426,6 +463,13 @@ bdrs_status cert_from_record(bdrs_solver s, const double* h, bool repair, bdrs_c
   if (out) *out = ce;
   if (ce.n_nonfinite > 0 || !std::isfinite(ce.L) || !std::isfinite(ce.U))
     return fail(BDRS_E_NUMERIC, "non-finite values in the certificate at iteration %lld", (long long)ce.k);
+  if (s->L.keep_best && ce.rel_gap < s->best_rel) {
+    // the state after iteration k (the certified one) becomes the retained state
+    const hipError_t e = copy_best(s, true);
+    if (e != hipSuccess) return hip_status(e, "keep best state");
+    s->best_rel = ce.rel_gap;
+    s->best_k = ce.k + 1;
+  }
   return BDRS_OK;
 }
 
@@ -647,6 +691,8 @@ bdrs_status bdrs_batch_solve(const bdrs_solver* solvers, int32_t count, void* wo
       return fail(BDRS_E_INVALID, "solvers[%d]: BDRS_F_REPAIR is not supported in batches", i);
     if (separate_cert(solvers[i]))
       return fail(BDRS_E_INVALID, "solvers[%d]: old-kernel and debiased variants are not batched", i);
+    if (solvers[i]->L.keep_best)
+      return fail(BDRS_E_INVALID, "solvers[%d]: BDRS_F_KEEP_BEST_STATE is not supported in batches", i);
   }
   hipStream_t st_b = nullptr;
   HIPCHK(hipStreamCreateWithFlags(&st_b, hipStreamNonBlocking));
@@ -709,7 +755,7 @@ bdrs_status bdrs_workspace_size(const bdrs_params* p, size_t* bytes) {
   bdrs_status st = check_sizes(p);
   if (st != BDRS_OK) return st;
   if (!bytes) return fail(BDRS_E_INVALID, "bytes is NULL");
-  *bytes = make_layout(p->m, p->n, p->dim).total;
+  *bytes = make_layout(p->m, p->n, p->dim, 0, 0, (p->flags & BDRS_F_KEEP_BEST_STATE) != 0).total;
   return BDRS_OK;
 }
 
@@ -771,7 +817,7 @@ bdrs_status create_from_host(const bdrs_params* p, const float* px, const float*
   if (std::fabs(sr - 1.0) > 1e-9) return fail(BDRS_E_INVALID, "r must sum to 1 (sum - 1 = %.3e)", sr - 1.0);
   if (std::fabs(sc - 1.0) > 1e-9) return fail(BDRS_E_INVALID, "c must sum to 1 (sum - 1 = %.3e)", sc - 1.0);
 
-  const Layout L = make_layout(m, n, dim, reserve_row, reserve_col);
+  const Layout L = make_layout(m, n, dim, reserve_row, reserve_col, (p->flags & BDRS_F_KEEP_BEST_STATE) != 0);
   if (p->workspace_bytes < L.total)  // e.g. the tuning table changed since the workspace was sized
     return fail(BDRS_E_NOMEM, "workspace too small: %zu bytes given, %zu needed", p->workspace_bytes, L.total);
   bdrs_solver s = new bdrs_solver_();
@@ -1184,6 +1230,23 @@ bdrs_status bdrs_profile_read(bdrs_solver s, int64_t* sweeps, double* ms, double
   if (sweeps) *sweeps = s->prof_sweeps;
   if (ms) *ms = tot;
   if (entries) *entries = s->prof_entries;
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_restore_best(bdrs_solver s, int64_t* iters_done) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  if (!s->L.keep_best) return fail(BDRS_E_INVALID, "the solver was created without BDRS_F_KEEP_BEST_STATE");
+  if (s->best_k < 0) return fail(BDRS_E_STATE, "no certificate yet: no state retained");
+  const LaunchCtx& c = s->ctx;
+  HIPCHK(copy_best(s, false));
+  long long k = s->best_k;
+  HIPCHK(hipMemcpyAsync(&c.ctrl->k, &k, sizeof k, hipMemcpyHostToDevice, c.stream));
+  s->k = k;
+  s->packed_rows = false;
+  const bdrs_status st = repack(s);
+  if (st != BDRS_OK) return st;
+  HIPCHK(hipStreamSynchronize(c.stream));
+  if (iters_done) *iters_done = k;
   return BDRS_OK;
 }
 

@@ -33,6 +33,9 @@ struct Layout {
   size_t c_abs, c_off, c_tile, c_A, c_perm, c_marg, c_logm, c_iperm, c_hint;
   size_t la, lah, lb1, lb2, lbh, lt0, lt1, mu, logs, pvec;
   size_t part, cert_part, cert_out, plan_row, plan_col, plan_stats, tile_count, tile_total;
+  // retained best state (BDRS_F_KEEP_BEST_STATE; 0 otherwise), in tile order
+  bool keep_best;
+  size_t best_la, best_lah, best_lb1, best_lb2, best_lbh, best_lt0, best_lt1, best_hr, best_hc;
 };
 
 // Split counts of the tuning table for this shape, if it holds an entry.
@@ -42,7 +45,7 @@ bool tuned_splits(int dim, int m, int n, int* splits_row, int* splits_col);
 int normalize_splits(int s, int ntiles_in);
 // Workspace layout; the partial records get room for at least reserve_row /
 // reserve_col splits (the autotuner's largest candidates).
-Layout make_layout(int m, int n, int dim, int reserve_row = 0, int reserve_col = 0);
+Layout make_layout(int m, int n, int dim, int reserve_row = 0, int reserve_col = 0, bool keep_best = false);
 bdrs_status check_sizes(const bdrs_params* p);
 // need = 0: the workspace must hold make_layout(m, n, dim)
 bdrs_status check_params(const bdrs_params* p, size_t need = 0);
@@ -109,4 +112,7 @@ struct bdrs_solver_ {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t blk_exec = nullptr;
   int blk_len = 0;
+  // BDRS_F_KEEP_BEST_STATE: relative gap of the retained state and its iteration count
+  double best_rel = INFINITY;
+  long long best_k = -1;
 };

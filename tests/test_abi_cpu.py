@@ -235,3 +235,16 @@ def test_variant_flags_need_lambda_one():
     h = ctypes.c_void_p()
     assert bdrs.lib().bdrs_create(ctypes.byref(p), ctypes.byref(h)) == bdrs.E_INVALID
     assert "lambda" in bdrs.last_error()
+
+
+def test_keep_best_state_adds_a_linear_region(saved_table):
+    m, n = 1000, 1200
+    a = bdrs.workspace_size(m, n, 2)
+    b = bdrs.workspace_size(m, n, 2, bdrs.F_KEEP_BEST_STATE)
+    # 7 float64 state vectors and 2 int32 hint vectors (padded), 256-byte aligned
+    assert a < b <= a + (7 * 8 + 2 * 4) * (m + n + 2 * 256) + 9 * 256
+
+
+def test_restore_best_rejects_null_solver():
+    assert bdrs.lib().bdrs_restore_best(None, None) == bdrs.E_INVALID
+    assert bdrs.last_error()
