@@ -281,6 +281,67 @@ typedef struct {
 BDRS_API bdrs_status bdrs_round(bdrs_solver s, bdrs_round_stats *out);
 
 /*
+ * Export of a feasible plan of the current iterate, exactly and in O(m + n)
+ * memory, as the factors of
+ *
+ *     P_ij = exp(u_i + v_j - C_ij / eps) + a_i b_j,   C_ij = s |x_i - y_j|^2.
+ *
+ * BDRS_PLAN_ROUNDED: G, the two-sided rounding of the state plan X^k that
+ *   bdrs_round prices (Altschuler, Weed and Rigollet 2017, Algorithm 2):
+ *   u = log alpha^k + log x, v = log beta^k + log y, a = e_r,
+ *   b = e_c / ||e_r||_1, eps = eta / (lambda k).
+ * BDRS_PLAN_REPAIRED: Z^ = Z diag(e) + p q^T / delta, the repair of the
+ *   intermediate plan Z = diag(alpha-hat) K diag(beta-tilde) of the last
+ *   finished iteration (proof of Prop. 3, feasible primal repair):
+ *   u = log alpha-hat, v = log beta-tilde + log e with
+ *   e_j = min(1, c_j / s_j), a = p, b = (c - s)_+ / delta (0 when
+ *   delta = 0), eps = the row update's temperature of that iteration; its
+ *   cost is the repaired cost of the certificate at that iteration.
+ *
+ * Both lie in Pi(r, c) up to the float32 sweeps' accuracy: the deficits that
+ * a and b carry are r and c minus row and column sums taken by the sweeps
+ * (relative error about 1e-6 per sum), so P 1 = r and P^T 1 = c hold to that
+ * relative accuracy entry by entry.
+ */
+#define BDRS_PLAN_ROUNDED 0
+#define BDRS_PLAN_REPAIRED 1
+
+typedef struct {
+  int32_t kind;          /* BDRS_PLAN_ROUNDED or BDRS_PLAN_REPAIRED */
+  int64_t k;             /* finished iterations of the state exported */
+  double eps;            /* temperature of the kernel part */
+  double cost_scale;     /* s of C_ij = s |x_i - y_j|^2 */
+  double cost;           /* <C, P> */
+  double mass;           /* mass of the rank-one part: ||e_r||_1 (rounded), delta (repaired) */
+} bdrs_plan_export;
+
+/* Writes the factors of the chosen feasible plan into caller device buffers
+ * (float64, original point order; NULL skips one): log_u and a (m),
+ * log_v and b (n); info (host, optional).  BDRS_E_INVALID for an unknown
+ * kind, BDRS_E_STATE before the first iteration, BDRS_E_NUMERIC when the
+ * plan's cost is not finite.  Runs three sweeps (rounded) or the
+ * certificate's column sweep and the repair's row sweep (repaired); uses the
+ * solver's sweep and certificate buffers, not its dual state or warm-start
+ * hints, so the iteration that follows is unchanged.  Synchronises the
+ * stream. */
+BDRS_API bdrs_status bdrs_export_plan(bdrs_solver s, int32_t kind, double *log_u, double *log_v,
+                                      double *a, double *b, bdrs_plan_export *info);
+
+/* Dense entries of a factored plan for the rows [row_begin, row_end) into
+ * out, a caller device buffer of (row_end - row_begin) x n float64,
+ * row-major, original point order: out[(i - row_begin) n + j] = P_ij from
+ * the factors above (device, original order; a and b both given or both
+ * NULL for no rank-one part) at temperature eps, with C_ij in float64 from
+ * the solver's stored float32 coordinates.  A large plan is written in
+ * strips of rows.  BDRS_E_INVALID for a NULL log_u or log_v, a NULL out
+ * with a non-empty range, a row range outside [0, m), eps not positive and
+ * finite, or n > 65535 * 256.  Write-bound (8 bytes per entry).
+ * Synchronises the stream. */
+BDRS_API bdrs_status bdrs_plan_entries(bdrs_solver s, const double *log_u, const double *log_v,
+                                       const double *a, const double *b, double eps,
+                                       int64_t row_begin, int64_t row_end, double *out);
+
+/*
  * Batched solving (many independent problems in one set of launches).
  * The problems are solver objects from bdrs_create (each with its own
  * workspace), all with the same dim, all at an iteration count that is a

@@ -39,8 +39,13 @@ EXPORTS = [
     "bdrs_server_wait", "bdrs_server_stats", "bdrs_server_now", "bdrs_server_destroy",
     "bdrs_get_hints", "bdrs_set_hints", "bdrs_autotune_workspace_size", "bdrs_autotune",
     "bdrs_tune_set", "bdrs_tune_get", "bdrs_tune_clear", "bdrs_plan", "bdrs_server_set_policy",
-    "bdrs_round", "bdrs_profile_evaluated", "bdrs_restore_best",
+    "bdrs_round", "bdrs_profile_evaluated", "bdrs_restore_best", "bdrs_export_plan",
+    "bdrs_plan_entries",
 ]
+
+PLAN_ROUNDED = 0
+PLAN_REPAIRED = 1
+PLAN_KINDS = {"rounded": PLAN_ROUNDED, "repaired": PLAN_REPAIRED}
 
 
 class Params(ctypes.Structure):
@@ -115,6 +120,16 @@ class RoundStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class PlanExport(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("k", ctypes.c_int64), ("eps", ctypes.c_double),
+        ("cost_scale", ctypes.c_double), ("cost", ctypes.c_double), ("mass", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class TuneEntry(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int32), ("m", ctypes.c_int32), ("n", ctypes.c_int32),
@@ -181,6 +196,9 @@ def lib() -> ctypes.CDLL:
         L.bdrs_round.argtypes = [vp, P(RoundStats)]
         L.bdrs_profile_evaluated.argtypes = [vp, P(ctypes.c_double)]
         L.bdrs_restore_best.argtypes = [vp, P(ctypes.c_int64)]
+        L.bdrs_export_plan.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, P(PlanExport)]
+        L.bdrs_plan_entries.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int64,
+                                        ctypes.c_int64, vp]
         L.bdrs_last_error.restype = ctypes.c_char_p
         L.bdrs_version.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -329,6 +347,32 @@ class Solver:
         st = RoundStats()
         check(lib().bdrs_round(self._h, ctypes.byref(st)))
         return st.as_dict()
+
+    def export_plan(self, kind: str = "rounded") -> dict:
+        """Factors of a feasible plan of the current iterate (float64, original
+        order): P_ij = exp(log_u_i + log_v_j - C_ij / eps) + a_i b_j.  kind
+        "rounded" is the two-sided rounding of the state plan, "repaired" the
+        repair of the last iteration's intermediate plan."""
+        torch = self._torch
+        dev = self._inputs[0].device
+        u, a = (torch.empty(self.m, dtype=torch.float64, device=dev) for _ in range(2))
+        v, b = (torch.empty(self.n, dtype=torch.float64, device=dev) for _ in range(2))
+        info = PlanExport()
+        check(lib().bdrs_export_plan(self._h, PLAN_KINDS[kind], _ptr(u), _ptr(v), _ptr(a), _ptr(b),
+                                     ctypes.byref(info)))
+        return dict(info=info.as_dict(), log_u=u, log_v=v, a=a, b=b)
+
+    def plan_entries(self, plan: dict, row_begin: int = 0, row_end=None):
+        """Dense rows [row_begin, row_end) of an exported plan, (rows, n) float64."""
+        torch = self._torch
+        row_end = self.m if row_end is None else int(row_end)
+        out = torch.empty((max(row_end - int(row_begin), 0), self.n), dtype=torch.float64,
+                          device=self._inputs[0].device)
+        f = lambda key: None if plan.get(key) is None else plan[key].to(torch.float64).contiguous()
+        u, v, a, b = f("log_u"), f("log_v"), f("a"), f("b")
+        check(lib().bdrs_plan_entries(self._h, _ptr(u), _ptr(v), _ptr(a), _ptr(b),
+                                      float(plan["info"]["eps"]), int(row_begin), row_end, _ptr(out)))
+        return out
 
     def profile(self, enable: bool) -> None:
         check(lib().bdrs_profile(self._h, 1 if enable else 0))

@@ -106,6 +106,7 @@ Layout make_layout(int m, int n, int dim, int reserve_row, int reserve_col, bool
   L.cert_out = take(sizeof(double) * kCertSlots);
   L.plan_row = take(sizeof(double) * L.R.np);
   L.plan_col = take(sizeof(double) * L.C.np);
+  L.plan_aux = take(sizeof(double) * L.R.np);
   L.plan_stats = take(sizeof(double) * kCertSlots);
   L.tile_total = take(sizeof(unsigned long long));
   if (keep_best) {
@@ -321,6 +322,7 @@ void fill_ctx(bdrs_solver s) {
   c.cert_blocks = L.cert_blocks;
   c.plan_row = (double*)(base + L.plan_row);
   c.plan_col = (double*)(base + L.plan_col);
+  c.plan_aux = (double*)(base + L.plan_aux);
   c.plan_stats = (double*)(base + L.plan_stats);
   c.tile_count = nullptr;  // set for profiled sweeps only
   c.tile_total = nullptr;
@@ -1132,14 +1134,12 @@ bdrs_status bdrs_plan(bdrs_solver s, double* bary, double* row_marg, double* col
   return repack(s);
 }
 
-bdrs_status bdrs_round(bdrs_solver s, bdrs_round_stats* out) {
-  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
-  if (!out) return fail(BDRS_E_INVALID, "out is NULL");
-  bdrs_status st = sync_k(s);
-  if (st != BDRS_OK) return st;
-  if (s->k < 1) return fail(BDRS_E_STATE, "rounding needs at least one finished iteration");
+// Two-sided rounding of the state plan X = diag(alpha) K diag(beta) at eps
+// (Altschuler, Weed and Rigollet 2017, Algorithm 2) in three sweeps: log x in
+// plan_row, log y in plan_col, e_r in plan_aux, e_c in mu, <C, G> and
+// ||e_r||_1 in plan_stats[8..11].  The rows are left packed with other weights.
+bdrs_status enqueue_round(bdrs_solver s, double eps) {
   const LaunchCtx& c = s->ctx;
-  const double eps = s->prm.eta / (s->prm.lambda * (double)s->k);  // the state plan's kernel
   hipError_t e;
   // 1: row sums of X and x = min(1, r / X 1)
   if ((e = launch_pack_state(c, false, eps)) != hipSuccess) return hip_status(e, "pack beta");
@@ -1157,6 +1157,19 @@ bdrs_status bdrs_round(bdrs_solver s, bdrs_round_stats* out) {
   if ((e = launch_finish(c, false, kFinishRound3, s->L.splits_row, eps, nullptr, 0)) != hipSuccess)
     return hip_status(e, "cost finish");
   if ((e = launch_round_reduce(c)) != hipSuccess) return hip_status(e, "reduce");
+  s->packed_rows = false;
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_round(bdrs_solver s, bdrs_round_stats* out) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  if (!out) return fail(BDRS_E_INVALID, "out is NULL");
+  bdrs_status st = sync_k(s);
+  if (st != BDRS_OK) return st;
+  if (s->k < 1) return fail(BDRS_E_STATE, "rounding needs at least one finished iteration");
+  const double eps = s->prm.eta / (s->prm.lambda * (double)s->k);  // the state plan's kernel
+  if ((st = enqueue_round(s, eps)) != BDRS_OK) return st;
+  const LaunchCtx& c = s->ctx;
   double h[4];
   HIPCHK(hipMemcpyAsync(h, c.plan_stats + 8, sizeof h, hipMemcpyDeviceToHost, c.stream));
   HIPCHK(hipStreamSynchronize(c.stream));
@@ -1165,9 +1178,70 @@ bdrs_status bdrs_round(bdrs_solver s, bdrs_round_stats* out) {
   out->cost = h[0];
   out->cost_clipped = h[1];
   out->mass_moved = h[2];
-  s->packed_rows = false;
   if (!std::isfinite(h[0])) return fail(BDRS_E_NUMERIC, "non-finite rounded cost");
   return repack(s);
+}
+
+bdrs_status bdrs_export_plan(bdrs_solver s, int32_t kind, double* log_u, double* log_v, double* a, double* b,
+                             bdrs_plan_export* out) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  if (kind != BDRS_PLAN_ROUNDED && kind != BDRS_PLAN_REPAIRED) return fail(BDRS_E_INVALID, "unknown plan kind %d", kind);
+  bdrs_status st = sync_k(s);
+  if (st != BDRS_OK) return st;
+  if (s->k < 1) return fail(BDRS_E_STATE, "a plan needs at least one finished iteration");
+  const LaunchCtx& c = s->ctx;
+  hipError_t e;
+  double h[kCertSlots];
+  bdrs_plan_export info{};
+  info.kind = kind;
+  info.k = s->k;
+  info.cost_scale = s->prm.cost_scale;
+  if (kind == BDRS_PLAN_ROUNDED) {
+    const double eps = s->prm.eta / (s->prm.lambda * (double)s->k);
+    if ((st = enqueue_round(s, eps)) != BDRS_OK) return st;
+    if ((e = launch_export_factors(c, false, nullptr, log_u, log_v, a, b)) != hipSuccess)
+      return hip_status(e, "export factors");
+    HIPCHK(hipMemcpyAsync(h, c.plan_stats + 8, 4 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    info.eps = eps;
+    info.cost = h[0];
+    info.mass = h[2];
+    if ((st = repack(s)) != BDRS_OK) return st;
+  } else {
+    // the certificate's column statistics and the repair of the last finished iteration
+    if ((st = enqueue_cert_only(s)) != BDRS_OK) return st;
+    if ((e = launch_cert_reduce(c)) != hipSuccess) return hip_status(e, "cert reduce");
+    if ((st = enqueue_repair(s)) != BDRS_OK) return st;
+    if ((e = launch_export_factors(c, true, c.st.lt[(s->k - 1) & 1], log_u, log_v, a, b)) != hipSuccess)
+      return hip_status(e, "export factors");
+    HIPCHK(hipMemcpyAsync(h, c.cert_out, sizeof h, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    info.eps = h[1];
+    info.cost = h[8];
+    info.mass = h[4];
+  }
+  if (out) *out = info;
+  if (!std::isfinite(info.cost)) return fail(BDRS_E_NUMERIC, "non-finite plan cost");
+  return BDRS_OK;
+}
+
+bdrs_status bdrs_plan_entries(bdrs_solver s, const double* log_u, const double* log_v, const double* a,
+                              const double* b, double eps, int64_t row_begin, int64_t row_end, double* out) {
+  if (!s) return fail(BDRS_E_INVALID, "solver is NULL");
+  if (!log_u || !log_v || (!out && row_end > row_begin))
+    return fail(BDRS_E_INVALID, "log_u, log_v and out must not be NULL");
+  if ((a == nullptr) != (b == nullptr)) return fail(BDRS_E_INVALID, "a and b must both be given or both be NULL");
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(BDRS_E_INVALID, "eps must be positive and finite");
+  const LaunchCtx& c = s->ctx;
+  if (row_begin < 0 || row_end < row_begin || row_end > c.rows.count)
+    return fail(BDRS_E_INVALID, "row range [%lld, %lld) outside [0, %d)", (long long)row_begin, (long long)row_end,
+                c.rows.count);
+  if (c.cols.count > 65535 * kBlock) return fail(BDRS_E_INVALID, "dense entries need n <= %d", 65535 * kBlock);
+  const hipError_t e = launch_plan_entries(c, log_u, log_v, a, b, s->prm.cost_scale / eps, row_begin,
+                                           row_end - row_begin, out);
+  if (e != hipSuccess) return hip_status(e, "plan entries");
+  HIPCHK(hipStreamSynchronize(c.stream));
+  return BDRS_OK;
 }
 
 bdrs_status bdrs_get_hints(bdrs_solver s, int32_t* row_hint, int32_t* col_hint) {

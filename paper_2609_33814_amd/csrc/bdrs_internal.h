@@ -143,6 +143,7 @@ struct LaunchCtx {
   int cert_blocks;
   double* plan_row;    // [rows.np] row sums of the state plan (tile order)
   double* plan_col;    // [cols.np] column sums of the state plan (tile order)
+  double* plan_aux;    // [rows.np] the rounding's row deficits e_r (tile order)
   double* plan_stats;  // [kCertSlots] marginal-error statistics
   double origin[3];    // common origin of the stored coordinates
   // profiling only (null otherwise): one slot per sweep wavefront receiving
@@ -184,6 +185,13 @@ hipError_t launch_plan_stats(const LaunchCtx& c);
 hipError_t launch_cert_reduce(const LaunchCtx& c);
 hipError_t launch_repair_pack(const LaunchCtx& c);
 hipError_t launch_repair_reduce(const LaunchCtx& c);
+// factors of the rounded (repaired = false) or repaired plan in original order;
+// null outputs are skipped
+hipError_t launch_export_factors(const LaunchCtx& c, bool repaired, const double* lt_prev, double* u, double* v,
+                                 double* a, double* b);
+// dense rows [row_begin, row_begin + nrows) of a factored plan (kap = cost scale / eps)
+hipError_t launch_plan_entries(const LaunchCtx& c, const double* u, const double* v, const double* a,
+                               const double* b, double kap, long long row_begin, long long nrows, double* out);
 hipError_t launch_scatter(const double* src, const int* perm, int count, double* dst, hipStream_t s);
 hipError_t launch_gather(const double* src, const int* perm, int np, double* dst, hipStream_t s);
 // hints: to original order (out[perm_out[p]] = perm_in[hint[p]]) and back

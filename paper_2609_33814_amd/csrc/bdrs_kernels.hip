@@ -38,6 +38,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace bdrs {
 
 namespace {
@@ -714,7 +716,9 @@ __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, 
       const double lcol = c.st.lb1[p] + mg.lse;
       const double ly = fmin(0.0, out.logmarg[p] - lcol);
       c.plan_col[p] = ly;
-      c.st.mu[p] = out.marg[p] - exp(lcol + ly);
+      // nonnegative by construction; the clamp removes an ulp of rounding
+      // where y_j = c_j / (X'^T 1)_j, so that every entry of G is >= 0
+      c.st.mu[p] = fmax(0.0, out.marg[p] - exp(lcol + ly));
     }
     return;
   }
@@ -722,7 +726,7 @@ __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, 
     // X'' = diag(x) X diag(y): row deficit r_i - (X'' 1)_i and sum_j X''_ij C_ij
     if (real) {
       const double row2 = exp(c.st.la[p] + c.plan_row[p] + mg.lse);
-      c.plan_row[p] = out.marg[p] - row2;
+      c.plan_aux[p] = fmax(0.0, out.marg[p] - row2);
       c.st.pvec[p] = row2 * ctrl->scale * mg.N / mg.S;
     }
     return;
@@ -1094,13 +1098,13 @@ __global__ __launch_bounds__(kBlock) void k_repair_final(LaunchCtx c) {
 // Rounded cost: sum_i cost_i + e_r^T C e_c / ||e_r||_1 with the squared
 // Euclidean closed form e_r^T C e_c = s [ (sum e_c)(sum e_r |x|^2) +
 // (sum e_r)(sum e_c |y|^2) - 2 (sum e_r x).(sum e_c y) ].  Row deficits in
-// plan_row, row costs in pvec, column deficits in mu (kFinishRound3 / 2).
+// plan_aux, row costs in pvec, column deficits in mu (kFinishRound3 / 2).
 __global__ __launch_bounds__(kBlock) void k_round_partial(LaunchCtx c) {
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int stride = gridDim.x * kBlock;
   const int dim = c.dim;
   for (int p = blockIdx.x * kBlock + threadIdx.x; p < c.rows.count; p += stride) {
-    const double er = c.plan_row[p];
+    const double er = c.plan_aux[p];
     double n2 = 0.0;
     for (int d = 0; d < dim; ++d) {
       const double xd = c.rows.abs[(size_t)d * c.rows.np + p];
@@ -1198,6 +1202,76 @@ __global__ void k_gather(const double* __restrict__ src, const int* __restrict__
                          double* __restrict__ dst) {
   const int p = blockIdx.x * kBlock + threadIdx.x;
   if (p < np) dst[p] = src[perm[p]];
+}
+
+// Factors of a feasible plan X_ij = exp(u_i + v_j - C_ij / eps) + a_i b_j, in
+// original order.  Rounded state plan (Altschuler, Weed and Rigollet 2017,
+// Algorithm 2): u = log alpha + log x, v = log beta + log y, a = e_r,
+// b = e_c / ||e_r||_1.  Repaired intermediate plan (proof of Prop. 3):
+// u = log alpha-hat, v = log t + log e with e_j = min(1, c_j / s_j), a = p,
+// b = (c - s)_+ / delta.  lt_prev: log t of the last row update (repair only).
+__global__ void k_export_factors(LaunchCtx c, int repaired, const double* __restrict__ lt_prev,
+                                 double* __restrict__ u, double* __restrict__ v, double* __restrict__ a,
+                                 double* __restrict__ b) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p < c.rows.count) {
+    const int i = c.rows.perm[p];
+    if (u) u[i] = repaired ? c.st.lah[p] : c.st.la[p] + c.plan_row[p];
+    if (a) a[i] = repaired ? c.st.pvec[p] : c.plan_aux[p];
+  }
+  if (p < c.cols.count) {
+    const int j = c.cols.perm[p];
+    if (repaired) {
+      const double ls = c.st.logs[p];
+      const double delta = c.cert_out[4];
+      if (v) v[j] = lt_prev[p] + fmin(0.0, c.cols.logmarg[p] - ls);
+      if (b) b[j] = delta > 0.0 ? fmax(c.cols.marg[p] - exp(ls), 0.0) / delta : 0.0;
+    } else {
+      const double mass = c.plan_stats[10];
+      if (v) v[j] = c.st.lb1[p] + c.plan_col[p];
+      if (b) b[j] = mass > 0.0 ? c.st.mu[p] / mass : 0.0;
+    }
+  }
+}
+
+// Dense rows [row_begin, row_begin + nrows) of a factored plan, row-major in
+// original order: out[(i - row_begin) n + j] = exp(u_i + v_j - kap |x_i - y_j|^2)
+// + a_i b_j, in float64 from the stored float32 coordinates.  One thread per
+// column holds y_j, v_j and b_j; a block walks kEntryRows rows at a time, the
+// row's point and factors being uniform across it.  Write-bound: 8 bytes per
+// entry.
+constexpr int kEntryRows = 8;
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_plan_entries(LaunchCtx c, const double* __restrict__ u,
+                                                         const double* __restrict__ v,
+                                                         const double* __restrict__ a,
+                                                         const double* __restrict__ b, double kap,
+                                                         long long row_begin, long long nrows,
+                                                         double* __restrict__ out) {
+  const int n = c.cols.count;
+  const int j = blockIdx.y * kBlock + threadIdx.x;
+  if (j >= n) return;
+  const int qj = c.cols.iperm[j];
+  double y[D];
+  for (int d = 0; d < D; ++d) y[d] = (double)c.cols.abs[(size_t)d * c.cols.np + qj];
+  const double vj = v[j];
+  const double bj = b ? b[j] : 0.0;
+  const long long blocks = (nrows + kEntryRows - 1) / kEntryRows;
+  for (long long rb = blockIdx.x; rb < blocks; rb += gridDim.x) {
+    const long long r0 = rb * kEntryRows;
+    const int rows = (int)min((long long)kEntryRows, nrows - r0);
+    for (int t = 0; t < rows; ++t) {
+      const long long i = row_begin + r0 + t;
+      const int qi = c.rows.iperm[i];
+      double d2 = 0.0;
+      for (int d = 0; d < D; ++d) {
+        const double e = (double)c.rows.abs[(size_t)d * c.rows.np + qi] - y[d];
+        d2 = fma(e, e, d2);
+      }
+      const double ai = a ? a[i] : 0.0;
+      out[(size_t)(r0 + t) * n + j] = exp(u[i] + vj - kap * d2) + ai * bj;
+    }
+  }
 }
 
 }  // namespace
@@ -1375,6 +1449,32 @@ hipError_t launch_repair_pack(const LaunchCtx& c) {
 hipError_t launch_repair_reduce(const LaunchCtx& c) {
   hipLaunchKernelGGL(k_repair_partial, dim3(c.cert_blocks), dim3(kBlock), 0, c.stream, c);
   hipLaunchKernelGGL(k_repair_final, dim3(1), dim3(kBlock), 0, c.stream, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_factors(const LaunchCtx& c, bool repaired, const double* lt_prev, double* u, double* v,
+                                 double* a, double* b) {
+  const int cnt = std::max(c.rows.count, c.cols.count);
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_export_factors, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, c.stream, c,
+                     repaired ? 1 : 0, lt_prev, u, v, a, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_entries(const LaunchCtx& c, const double* u, const double* v, const double* a,
+                               const double* b, double kap, long long row_begin, long long nrows, double* out) {
+  if (nrows <= 0 || c.cols.count <= 0) return hipSuccess;
+  const long long rblocks = (nrows + kEntryRows - 1) / kEntryRows;
+  const dim3 grid((unsigned)std::min(rblocks, 65536LL), (unsigned)((c.cols.count + kBlock - 1) / kBlock));
+#define BDRS_ENTRIES(DD)                                                                                 \
+  hipLaunchKernelGGL(k_plan_entries<DD>, grid, dim3(kBlock), 0, c.stream, c, u, v, a, b, kap, row_begin, \
+                     nrows, out)
+  switch (c.dim) {
+    case 1: BDRS_ENTRIES(1); break;
+    case 2: BDRS_ENTRIES(2); break;
+    default: BDRS_ENTRIES(3); break;
+  }
+#undef BDRS_ENTRIES
   return hipGetLastError();
 }
 

@@ -248,3 +248,11 @@ def test_keep_best_state_adds_a_linear_region(saved_table):
 def test_restore_best_rejects_null_solver():
     assert bdrs.lib().bdrs_restore_best(None, None) == bdrs.E_INVALID
     assert bdrs.last_error()
+
+
+def test_export_plan_rejects_null_solver_and_bad_kind():
+    L = bdrs.lib()
+    assert L.bdrs_export_plan(None, bdrs.PLAN_ROUNDED, None, None, None, None, None) == bdrs.E_INVALID
+    assert "NULL" in bdrs.last_error()
+    assert L.bdrs_plan_entries(None, None, None, None, None, 1.0, 0, 0, None) == bdrs.E_INVALID
+    assert bdrs.last_error()

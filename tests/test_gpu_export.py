@@ -1,0 +1,218 @@
+"""Export of a feasible plan (bdrs_export_plan / bdrs_plan_entries) against
+the oracle's dense plans built from the GPU's own dual state: the two-sided
+rounding of the state plan (Altschuler, Weed and Rigollet 2017, Algorithm 2)
+and the repair of the intermediate plan (proof of Prop. 3).
+
+Tolerances: the factors carry row / column sums taken by float32 sweeps
+(about 1e-6 relative each, from tile-centred float32 offsets), and the dense
+entries evaluate C_ij in float64 from the stored float32 coordinates
+(relative to a common origin), so an entry's exponent differs from the
+sweeps' by up to a few 1e-6: entries agree with the oracle to 1e-4 relative
+where they matter and in L1 (total mass 1), and the plans' marginals match r
+and c to 3e-5 relative per entry."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import alg1, lp, lse, plan, repair, rounding  # noqa: E402
+from paper_2609_33814_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def solver_for(prob, eta, lam=1.0, variant="dual_bdrs", repair_flag=False):
+    from paper_2609_33814_amd import bdrs
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda:0")
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=d)
+    return bdrs.Solver(t(prob.x, torch.float32), t(prob.y, torch.float32), t(prob.r, torch.float64),
+                       t(prob.c, torch.float64), prob.cost_scale, eta=eta, lam=lam, variant=variant,
+                       repair=repair_flag)
+
+
+def np64(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def check_feasible(P, r, c, rel_row, rel_col):
+    row, col = P.sum(axis=1), P.sum(axis=0)
+    er, ec = np.max(np.abs(row - r) / r), np.max(np.abs(col - c) / c)
+    print(f"marginals: max rel row {er:.2e} col {ec:.2e}")
+    assert np.all(P >= 0)
+    assert er <= rel_row and ec <= rel_col
+
+
+def check_entries(got, ref, rel=1e-4):
+    big = ref >= 1e-3 * ref.max()
+    e_big, e_l1 = np.max(np.abs(got[big] - ref[big]) / ref[big]), np.abs(got - ref).sum()
+    print(f"entries: max rel {e_big:.2e} L1 {e_l1:.2e}")
+    assert e_big <= rel and e_l1 <= 1e-4
+
+
+CASES = [
+    ("grid16_bdrs", lambda: inputs.grid_problem(16, 1, 2), 1.0, 1.0, "dual_bdrs", 50),
+    ("rand_d3_obdrs", lambda: inputs.random_problem(300, 517, 3, 1), 0.5, 1.5, "dual_bdrs", 12),
+    ("rand_d1_as", lambda: inputs.random_problem(257, 190, 1, 2), 0.5, 1.0, "annealed_sinkhorn", 20),
+    ("rand_d2_tiny", lambda: inputs.random_problem(5, 70, 2, 3), 0.3, 1.0, "dual_bdrs", 3),
+]
+
+
+@pytest.mark.parametrize("name,make,eta,lam,variant,iters", CASES, ids=[c[0] for c in CASES])
+def test_rounded_plan_matches_oracle(name, make, eta, lam, variant, iters):
+    prob = make()
+    sv = solver_for(prob, eta, lam, variant)
+    sv.step(iters)
+    st = sv.get_state()
+    ex = sv.export_plan("rounded")
+    info = ex["info"]
+    eps = plan.plan_temperature(eta, lam, iters)
+    assert info["k"] == iters and info["eps"] == pytest.approx(eps, rel=1e-15)
+    C = lse.cost_matrix(prob.x, prob.y, prob.cost_scale)
+    F = np.exp(np64(st["la"])[:, None] + np64(st["lb"])[None, :] - C / eps)
+    ref = rounding.dense_round(F, prob.r, prob.c)
+    # factors against the oracle's x, y, e_r, e_c
+    assert np.allclose(np.exp(np64(ex["log_u"]) - np64(st["la"])), ref["x"], rtol=1e-5, atol=0)
+    assert np.allclose(np.exp(np64(ex["log_v"]) - np64(st["lb"])), ref["y"], rtol=1e-5, atol=0)
+    assert np.max(np.abs(np64(ex["a"]) - ref["er"]) / prob.r) <= 1e-5
+    G = np64(sv.plan_entries(ex))
+    check_entries(G, ref["G"])
+    check_feasible(G, prob.r, prob.c, 3e-5, 3e-5)
+    assert abs(float((G * C).sum()) - info["cost"]) <= 1e-4 * info["cost"]
+    assert info["mass"] == pytest.approx(ref["mass"], rel=1e-3, abs=2e-6)
+    # the same computation as bdrs_round
+    assert sv.round()["cost"] == info["cost"]
+    sv.close()
+
+
+@pytest.mark.parametrize("lam", [1.0, 1.99])
+def test_repaired_plan_matches_oracle(lam):
+    prob = inputs.random_problem(140, 203, 2, 12)
+    C = lse.cost_matrix(prob.x, prob.y, prob.cost_scale)
+    pstar = lp.linprog_ot(C, prob.r, prob.c)
+    sv = solver_for(prob, eta=0.5, lam=lam)
+    sv.step(60)
+    ex = sv.export_plan("repaired")
+    info = ex["info"]
+    gs = sv.get_state()
+    eps = alg1.schedule(0.5, lam, 59)
+    assert info["k"] == 60 and info["eps"] == pytest.approx(eps, rel=1e-15)
+    rp = repair.dense_repair(prob.x, prob.y, prob.cost_scale, prob.r, prob.c, np64(gs["lah"]), np64(gs["lt"]), eps)
+    assert np.allclose(np64(ex["log_u"]), np64(gs["lah"]), rtol=0, atol=0)
+    assert np.allclose(np.exp(np64(ex["log_v"]) - np64(gs["lt"])), rp["e"], rtol=1e-5, atol=0)
+    p_gpu = np64(ex["a"])
+    assert np.max(np.abs(p_gpu - rp["p"]) / prob.r) <= 1e-5
+    # delta = 1/2 ||s - c||_1 and q = (c - s)_+ carry the column sums' absolute
+    # error (relative 1e-5 at most per sum), whatever the size of delta
+    delta = info["mass"]
+    assert abs(delta - rp["delta"]) <= 5e-6
+    q_gpu = np64(ex["b"]) * delta
+    assert np.all(np.abs(q_gpu - rp["q"]) <= 2e-5 * prob.c)
+    Zhat = np64(sv.plan_entries(ex))
+    check_entries(Zhat, rp["Zhat"])
+    # rows: Z~ 1 + p = Z 1 = r; columns: min(s, c) + q (sum p) / delta, where
+    # sum p (a row sweep) and delta (column sums) agree to their absolute error
+    ratio = p_gpu.sum() / delta
+    print(f"sum p / delta - 1 = {ratio - 1:.2e} (delta {delta:.2e})")
+    col = Zhat.sum(axis=0)
+    assert np.all(np.abs(col - prob.c) <= 3e-5 * prob.c + 1.01 * q_gpu * abs(ratio - 1))
+    assert np.abs(col - prob.c).sum() <= 2e-5
+    check_feasible(Zhat, prob.r, prob.c, 3e-5, np.inf)
+    assert abs(float((Zhat * C).sum()) - info["cost"]) <= 1e-4 * info["cost"]
+    assert abs(info["cost"] - rp["cost_Zhat"]) <= 1e-5 * rp["cost_Zhat"]
+    assert pstar <= info["cost"] * (1 + 1e-7)
+    # the same value the certificate reports with the repair on
+    tw = solver_for(prob, eta=0.5, lam=lam, repair_flag=True)
+    tw.step(60)
+    assert tw.certificate()["repaired_cost"] == info["cost"]
+    sv.close()
+    tw.close()
+
+
+def test_row_strips_equal_the_whole_and_iteration_unchanged():
+    """Strips of rows are bitwise the rows of the whole plan; exporting leaves
+    the next iterations bit for bit as without it."""
+    prob = inputs.random_problem(333, 290, 3, 5)
+    a = solver_for(prob, 0.4, 1.5)
+    b = solver_for(prob, 0.4, 1.5)
+    a.step(25)
+    b.step(25)
+    for kind in ("rounded", "repaired"):
+        ex = a.export_plan(kind)
+        whole = a.plan_entries(ex)
+        parts = [a.plan_entries(ex, lo, min(lo + 64, a.m)) for lo in range(0, a.m, 64)]
+        assert torch.equal(torch.cat(parts), whole)
+        assert torch.equal(a.plan_entries(ex, 100, 101), whole[100:101])
+        assert a.plan_entries(ex, 7, 7).shape == (0, a.n)
+        # without the rank-one part: the clipped plan alone
+        clip = a.plan_entries({k: ex[k] for k in ("log_u", "log_v", "info")})
+        assert torch.all(clip <= whole) and torch.all(clip >= 0)
+    a.step(30)
+    b.step(30)
+    sa, sb = a.get_state(), b.get_state()
+    for key in ("la", "lb", "lb_prev", "lah", "lbh", "lt"):
+        assert torch.equal(sa[key], sb[key]), key
+    a.close()
+    b.close()
+
+
+def test_export_errors():
+    from paper_2609_33814_amd import bdrs
+    prob = inputs.random_problem(64, 80, 2, 4)
+    sv = solver_for(prob, 0.5)
+    with pytest.raises(bdrs.BdrsError, match="finished iteration"):
+        sv.export_plan("rounded")
+    sv.step(3)
+    L = bdrs.lib()
+    assert L.bdrs_export_plan(sv.handle, 7, None, None, None, None, None) == bdrs.E_INVALID
+    assert "kind" in bdrs.last_error()
+    ex = sv.export_plan("rounded")
+    with pytest.raises(bdrs.BdrsError, match="row range"):
+        sv.plan_entries(ex, 10, 65)
+    with pytest.raises(bdrs.BdrsError, match="both"):
+        sv.plan_entries({"log_u": ex["log_u"], "log_v": ex["log_v"], "a": ex["a"], "info": ex["info"]})
+    with pytest.raises(bdrs.BdrsError, match="eps"):
+        sv.plan_entries(dict(ex, info=dict(ex["info"], eps=0.0)))
+    sv.close()
+
+
+@pytest.mark.parametrize("kind", ["rounded", "repaired"])
+def test_full_size_grid128_dense_export(kind):
+    """The 128 x 128 grid pair (m = n = 16384, 2.1 GB dense) after 300
+    iterations at eta = 0.1: sampled strips of rows equal the factored form
+    evaluated by the oracle's float64 cost on the caller's coordinates, and
+    the whole dense plan has marginals r and c (sums taken on the GPU)."""
+    prob = inputs.c2_problem()
+    sv = solver_for(prob, 0.1, 1.0)
+    sv.step(300)
+    ex = sv.export_plan(kind)
+    eps = ex["info"]["eps"]
+    u, v, a, b = (np64(ex[k]) for k in ("log_u", "log_v", "a", "b"))
+    for lo in (0, 8191, sv.m - 40):
+        hi = lo + 40
+        got = np64(sv.plan_entries(ex, lo, hi))
+        C = lse.cost_block(prob.x[lo:hi], prob.y, prob.cost_scale)
+        ref = np.exp(u[lo:hi, None] + v[None, :] - C / eps) + a[lo:hi, None] * b[None, :]
+        big = ref >= 1e-6 * ref.max()
+        assert np.max(np.abs(got[big] - ref[big]) / ref[big]) <= 2e-5, lo
+        assert np.abs(got - ref).sum() <= 1e-5 * ref.sum()
+    P = sv.plan_entries(ex)
+    r = torch.as_tensor(prob.r, device=P.device)
+    c = torch.as_tensor(prob.c, device=P.device)
+    row_err = float(((P.sum(dim=1) - r).abs() / r).max())
+    col_err = float(((P.sum(dim=0) - c).abs() / c).max())
+    print(f"{kind}: eps {eps:.3e} max rel marginal error row {row_err:.2e} col {col_err:.2e}")
+    assert float(P.min()) >= 0.0
+    assert row_err <= 3e-5
+    if kind == "rounded":
+        assert col_err <= 3e-5
+    else:
+        assert float((P.sum(dim=0) - c).abs().sum()) <= 2e-5
+    cost_dense = 0.0
+    for lo in range(0, sv.m, 2048):
+        C = torch.as_tensor(lse.cost_block(prob.x[lo:lo + 2048], prob.y, prob.cost_scale), device=P.device)
+        cost_dense += float((P[lo:lo + 2048] * C).sum())
+    assert abs(cost_dense - ex["info"]["cost"]) <= 1e-4 * ex["info"]["cost"]
+    del P
+    sv.close()
