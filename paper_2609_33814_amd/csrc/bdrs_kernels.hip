@@ -534,37 +534,43 @@ __device__ __forceinline__ Merged merge_splits(const PartialRec* __restrict__ pa
   return r;
 }
 
-__device__ __forceinline__ float norm2_off(const float* __restrict__ off, int dim, int p) {
-  const int t = p / kTile, q = p % kTile;
-  float s = 0.0f;
-  for (int d = 0; d < dim; ++d) {
-    const float b = off[((size_t)t * dim + d) * kTile + q];
-    s = fmaf(b, b, s);
-  }
-  return s;
-}
-
 // A_p = log2(e) w - kappa2 |b_p|^2 in float64 (-inf on padding or for w = -inf);
 // stores the tile maximum (float64) and A_p minus that maximum (float32), and
 // a plane fit w2 ~ alpha + gamma . b of the tile's log2 weights w2 = log2(e) w
 // with its largest residual rho (so w2 <= alpha + gamma . b + rho holds for
 // every point of the tile, whatever the fit).  The sweep turns it into an
 // upper bound of its exponents.  Called by whole wavefronts (one tile each).
+// Offsets of point p from its tile centre (0 past the real points); the
+// epilogues request them before they wait for the split records.
+// Three loads at clamped (valid) addresses whatever dim and p are, zeroed by a
+// multiplication (offsets are finite) rather than a select, so that every
+// loaded value is used and the loads issue together.
+__device__ __forceinline__ void load_offsets(const SideDev& sd, int dim, int p, float bo[3]) {
+  const int t = min(p, sd.count - 1) / kTile, q = p % kTile;
+  const float* base = sd.off + (size_t)t * dim * kTile + q;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float v = base[(size_t)min(d, dim - 1) * kTile];
+    bo[d] = v * ((p < sd.count && d < dim) ? 1.0f : 0.0f);
+  }
+}
+
 template <int D>
-__device__ __forceinline__ void pack_weight_d(const SideDev& sd, int p, double w, double kap2) {
+__device__ __forceinline__ void pack_weight_d(const SideDev& sd, int p, double w, double kap2, const float bo[3]) {
   constexpr int dim = D;
   const bool live = p < sd.count && w > -INFINITY;
-  const int t = p / kTile, q = p % kTile;
+  const int t = p / kTile;
   double A = -INFINITY, w2 = 0.0;
   double b[D];
+  float n2 = 0.0f;
 #pragma unroll
-  for (int d = 0; d < D; ++d) b[d] = 0.0;
-  if (p < sd.count) {
-    for (int d = 0; d < dim; ++d) b[d] = (double)sd.off[((size_t)t * dim + d) * kTile + q];
+  for (int d = 0; d < D; ++d) {
+    b[d] = (double)bo[d];
+    n2 = fmaf(bo[d], bo[d], n2);
   }
   if (live) {
     w2 = kLog2eD * w;
-    A = w2 - kap2 * (double)norm2_off(sd.off, dim, p);
+    A = w2 - kap2 * (double)n2;
   }
   if (p >= sd.ntiles * kTile) return;
   const double m = wave_max(A);
@@ -633,10 +639,17 @@ __device__ __forceinline__ void pack_weight_d(const SideDev& sd, int p, double w
   }
 }
 
+__device__ __forceinline__ void pack_weight(const SideDev& sd, int dim, int p, double w, double kap2,
+                                            const float bo[3]) {
+  if (dim == 1) pack_weight_d<1>(sd, p, w, kap2, bo);
+  else if (dim == 2) pack_weight_d<2>(sd, p, w, kap2, bo);
+  else pack_weight_d<3>(sd, p, w, kap2, bo);
+}
+
 __device__ __forceinline__ void pack_weight(const SideDev& sd, int dim, int p, double w, double kap2) {
-  if (dim == 1) pack_weight_d<1>(sd, p, w, kap2);
-  else if (dim == 2) pack_weight_d<2>(sd, p, w, kap2);
-  else pack_weight_d<3>(sd, p, w, kap2);
+  float bo[3];
+  load_offsets(sd, dim, p, bo);
+  pack_weight(sd, dim, p, w, kap2, bo);
 }
 
 // Merge of the barycentric partials of output p: shift, shifted sum and the
@@ -687,11 +700,24 @@ __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, 
     return;
   }
   const bool cert = (kind == kFinishColCert || kind == kFinishCertOnly);
+  const bool iter_kind = kind == kFinishRow || kind == kFinishCol || kind == kFinishColCert;
+  // An epilogue runs one wavefront per output tile, so its time is the number
+  // of memory round trips: what the iteration's epilogues read that does not
+  // depend on the merge (control block, marginal, dual state, the offsets the
+  // packing needs) is requested before the split records are waited for.
+  // Unconditional loads (p < np, and every array read here holds np entries
+  // of the output side): a load under a branch is waited for there.
+  const Ctrl cv = *c.ctrl;
+  float bo[3];
+  load_offsets(out, c.dim, p, bo);
+  const double* s_arr = transpose ? c.st.lb1 : c.st.la;
+  const double* t0_arr = transpose ? c.st.lt[0] : c.st.la;
+  const double* t1_arr = transpose ? c.st.lt[1] : c.st.la;
+  const double pre_lm = out.logmarg[p], pre_s = s_arr[p], pre_t0 = t0_arr[p], pre_t1 = t1_arr[p];
   const Merged mg = merge_splits(c.part.rec, splits, np, p);
   // the warm start of the next sweep of this side: only the iteration's own sweeps set it
-  const bool iter_kind = kind == kFinishRow || kind == kFinishCol || kind == kFinishColCert;
   if (real && iter_kind && mg.J >= 0) out.hint[p] = mg.J;
-  const Ctrl* ctrl = c.ctrl;
+  const Ctrl* ctrl = &cv;
   const long long k = ctrl->k + kofs;  // this iteration: the block's first plus the offset
   const double lam = ctrl->lam;
 
@@ -750,43 +776,47 @@ __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, 
     const double kap2 = kLog2eD * ctrl->scale / eps;
     double colw = 0.0;
     if (real) {
-      const double lah = out.logmarg[p] - mg.lse;
+      const double lah = pre_lm - mg.lse;
       c.st.lah[p] = lah;
       if (ctrl->variant & kVarDebiased) {
         // debiased row update: log a^k = theta_k log a^{k-1} + log r - LSE, theta_k = 0 (k <= 1), 1/k
         const double theta = k <= 1 ? 0.0 : 1.0 / (double)k;
-        colw = theta * c.st.la[p] + lah;
+        colw = theta * pre_s + lah;
         c.st.la[p] = colw;
       } else {
-        c.st.la[p] = (1.0 - lam) * c.st.la[p] + lam * lah;
+        // one rounded product fused into the other: fixed whatever the
+        // compiler's contraction (the result is exact for lambda = 1)
+        c.st.la[p] = fma(lam, lah, (1.0 - lam) * pre_s);
         colw = lah;
       }
     }
     // weights of the column sweep of the same iteration: log alpha-hat (the
     // debiased variant: its row scaling a^k)
-    pack_weight(c.rows, c.dim, p, colw, kap2);
+    pack_weight(c.rows, c.dim, p, colw, kap2, bo);
     return;
   }
   // column epilogue (plain or certificate)
   const int cur = (int)(k & 1), nxt = (int)((k + 1) & 1);
+  double lt_next = 0.0;
   if (real) {
-    const double lbh = out.logmarg[p] - mg.lse;         // log beta-hat^k = log c - LSE
-    const double lb1 = c.st.lb1[p];
-    const double lb = (1.0 - lam) * lb1 + lam * lbh;    // log beta^k
+    const double lbh = pre_lm - mg.lse;                 // log beta-hat^k = log c - LSE
+    const double lb1 = pre_s;
+    const double lb = fma(lam, lbh, (1.0 - lam) * lb1);  // log beta^k (rounding as for alpha)
     if (cert) {
       // Algorithm 2: mu_j = N_j / D_j, d_j = M_j + log D_j, log s_j = log t_j + d_j
       c.st.mu[p] = ctrl->scale * mg.N / mg.S;
-      c.st.logs[p] = c.st.lt[cur][p] + mg.lse;
+      c.st.logs[p] = (cur ? pre_t1 : pre_t0) + mg.lse;
     }
     c.st.lbh[p] = lbh;
     c.st.lb2[p] = lb1;
     c.st.lb1[p] = lb;
     // momentum for iteration k+1: log beta-tilde^k = log beta^k + (log beta^k - log beta^{k-1}) / lambda
-    c.st.lt[nxt][p] = (ctrl->variant & kVarNoMomentum) ? lb : lb + (lb - lb1) / lam;
+    lt_next = (ctrl->variant & kVarNoMomentum) ? lb : lb + (lb - lb1) / lam;
+    c.st.lt[nxt][p] = lt_next;
   }
   const double eps1 = eps_row_of(ctrl, -1.0, kofs + 1);
   const double kap2n = kLog2eD * ctrl->scale / eps1;
-  pack_weight(c.cols, c.dim, p, real ? c.st.lt[nxt][p] : 0.0, kap2n);
+  pack_weight(c.cols, c.dim, p, lt_next, kap2n, bo);
 
 }
 
