@@ -494,7 +494,7 @@ __device__ __forceinline__ Merged merge_splits(const PartialRec* __restrict__ pa
   constexpr int G = 16;
   double mx = -INFINITY, S = 0.0, N = 0.0;
   int J = -1;
-  for (int s0 = 0; s0 < splits; s0 += G) {
+  auto batch = [&](int s0) {
     PartialRec q[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -517,14 +517,18 @@ __device__ __forceinline__ Merged merge_splits(const PartialRec* __restrict__ pa
       mx = bm;
       J = bj;
     }
-    if (mx == -INFINITY) continue;  // nothing so far
+    if (mx == -INFINITY) return;  // nothing so far
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const double w = (double)fast_exp2((float)(q[g].M - mx));  // 0 for an empty or masked split
       S += w * (double)q[g].S;
       N += w * (double)q[g].N;
     }
-  }
+  };
+  // the first batch outside the loop: at a loop header the wait counts are
+  // merged conservatively, which would wait for the loads issued before it
+  batch(0);
+  for (int s0 = G; s0 < splits; s0 += G) batch(s0);
   Merged r{-INFINITY, 0.0, 0.0, -1};
   if (mx == -INFINITY) return r;  // empty sum
   r.S = S;
