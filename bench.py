@@ -393,7 +393,11 @@ def ablation_mode(args) -> int:
     0.1, lambda = 1: every row-update variant run to a 1% certified relative
     gap (cap 20000 iterations, certificate every 50); the last iterate's
     state plan is also rounded onto Pi(r, c), the feasible cost the ablation
-    compares."""
+    compares.  With --round-curve a second run of each variant rounds its
+    state plan after every iteration (outside any timing, as in the
+    ablation) and reports the feasible cost f_k at log-spaced k, its minimum
+    and (f_k - L) / f_k against the largest certified lower bound L of all
+    variants (which bounds the gap to the optimum from above)."""
     import numpy as np
     import torch
     from paper_2609_33814_amd import bdrs, inputs
@@ -416,6 +420,27 @@ def ablation_mode(args) -> int:
                      "rounded_cost": rd["cost"], "rounded_rel_gap": (rd["cost"] - ce["L_best"]) / rd["cost"]}
         print(f"[bench] {name}: {out[name]}", flush=True)
         sv.close()
+        if args.round_curve:
+            K = out[name]["iterations"]
+            sv = bdrs.Solver(X, Y, R, C, prob.cost_scale, eta=ETA, variant=name)
+            f = np.empty(K)
+            for k in range(K):
+                sv.step(1)
+                f[k] = sv.round()["cost"]
+            sv.close()
+            out[name]["_f"] = f
+            print(f"[bench] {name}: rounded after each of {K} iterations, min f {f.min():.6g} "
+                  f"at k = {int(f.argmin()) + 1}", flush=True)
+    if args.round_curve:
+        L = max(v["L_best"] for v in out.values())
+        for name, v in out.items():
+            f = v.pop("_f")
+            ks = sorted({min(int(round(10 ** (e / 4))), len(f)) for e in range(0, 4 * 5)} | {len(f)})
+            v["rounded_curve"] = {"k": ks, "f": [float(f[k - 1]) for k in ks],
+                                  "gap_vs_L": [float((f[k - 1] - L) / f[k - 1]) for k in ks]}
+            v["rounded_min"] = float(f.min())
+            v["rounded_min_gap_vs_L"] = float((f.min() - L) / f.min())
+        print(f"[bench] largest certified lower bound over the variants: L = {L:.9g}", flush=True)
     line = {
         "metric": "iterations and seconds to a 1% certified relative gap per row-update variant",
         "value": out["dual_bdrs"]["seconds"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
@@ -445,6 +470,8 @@ def main() -> int:
                          "colour transfer; colour10m: 10M points, per-iteration time; ablation: "
                          "row-update variants to a 1%% gap")
     ap.add_argument("--colour-iters", type=int, default=100)
+    ap.add_argument("--round-curve", action="store_true",
+                    help="ablation: also round each variant's state plan after every iteration")
     ap.add_argument("--serve-sides", default="32,64,128", help="grid sides of the serve requests")
     ap.add_argument("--serve-plain", action="store_true",
                     help="also serve with arrival-order admission (no size-aware policy)")
