@@ -545,13 +545,13 @@ BatchLayout batch_layout(const std::vector<bdrs_solver>& sv) {
 size_t BatchEngine::bytes_for(const std::vector<bdrs_solver>& members) { return batch_layout(members).total; }
 
 BatchEngine::~BatchEngine() {
-  if (exec_) hipGraphExecDestroy(exec_);
+  if (exec_) (void)hipGraphExecDestroy(exec_);  // teardown: nothing to report
 }
 
 hipError_t BatchEngine::bind(const std::vector<bdrs_solver>& members, char* ws, int block_iters, bool use_graph,
                              hipStream_t st) {
   if (exec_) {
-    hipGraphExecDestroy(exec_);
+    (void)hipGraphExecDestroy(exec_);
     exec_ = nullptr;
   }
   members_ = members;
@@ -601,7 +601,7 @@ hipError_t BatchEngine::bind(const std::vector<bdrs_solver>& members, char* ws, 
       if (r == hipSuccess) r = r2;
     }
     if (r == hipSuccess) r = hipGraphInstantiate(&exec_, g, nullptr, nullptr, 0);
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
   }
   return r;
 }
@@ -742,8 +742,9 @@ bdrs_status bdrs_batch_solve(const bdrs_solver* solvers, int32_t count, void* wo
       }
     }
   }
-  hipStreamSynchronize(st_b);
-  hipStreamDestroy(st_b);
+  const hipError_t es = hipStreamSynchronize(st_b);  // also reports a fault of the last block
+  if (e == hipSuccess) e = es;
+  (void)hipStreamDestroy(st_b);
   if (e != hipSuccess) return fail(BDRS_E_DEVICE, "HIP error %s in batch solve", hipGetErrorString(e));
   for (int i = 0; i < count; ++i) solvers[i]->packed_rows = true;
   return result;
@@ -931,7 +932,7 @@ bdrs_status bdrs_certificate(bdrs_solver s, bdrs_cert* out) {
 bdrs_status launch_block_graph(bdrs_solver s, int L) {
   if (!s->blk_exec || s->blk_len != L) {
     if (s->blk_exec) {
-      hipGraphExecDestroy(s->blk_exec);
+      (void)hipGraphExecDestroy(s->blk_exec);
       s->blk_exec = nullptr;
       s->blk_len = 0;
     }
@@ -950,7 +951,7 @@ bdrs_status launch_block_graph(bdrs_solver s, int L) {
     }
     s->ctx.stream = user;
     if (e == hipSuccess && st == BDRS_OK) e = hipGraphInstantiate(&s->blk_exec, g, nullptr, nullptr, 0);
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     if (st != BDRS_OK) return st;
     if (e != hipSuccess) {
       s->blk_exec = nullptr;
@@ -1327,9 +1328,10 @@ bdrs_status bdrs_restore_best(bdrs_solver s, int64_t* iters_done) {
 bdrs_status bdrs_destroy(bdrs_solver s) {
   if (!s) return BDRS_OK;
   hipError_t e = hipStreamSynchronize(s->ctx.stream);
-  for (hipEvent_t ev : s->ev_pool) hipEventDestroy(ev);
-  if (s->blk_exec) hipGraphExecDestroy(s->blk_exec);
-  if (s->cap_stream) hipStreamDestroy(s->cap_stream);
+  // teardown: nothing to report
+  for (hipEvent_t ev : s->ev_pool) (void)hipEventDestroy(ev);
+  if (s->blk_exec) (void)hipGraphExecDestroy(s->blk_exec);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
   if (e != hipSuccess) return hip_status(e, "destroy");
   return BDRS_OK;

@@ -143,7 +143,7 @@ void finish(bdrs_server_* sv, const std::shared_ptr<Request>& rq, int status) {
 }  // namespace
 
 void bdrs_server_::run() {
-  hipSetDevice(device);
+  const bool dev_ok = hipSetDevice(device) == hipSuccess;  // else every request fails with E_DEVICE
   BatchEngine eng;
   size_t eng_off = 0, eng_bytes = 0;
   bool eng_valid = false;
@@ -162,6 +162,12 @@ void bdrs_server_::run() {
       while (pick != queue.end() && big_work > 0 && big_running && (*pick)->work > big_work) ++pick;
       if (pick == queue.end()) break;
       std::shared_ptr<Request> rq = *pick;
+      if (!dev_ok) {
+        queue.erase(pick);
+        finish(this, rq, BDRS_E_DEVICE);
+        cv_done.notify_all();
+        continue;
+      }
       size_t off = 0;
       if (!alloc->alloc(rq->bytes, &off)) break;  // the candidate waits for memory; nothing passes it
       queue.erase(pick);
@@ -389,8 +395,9 @@ bdrs_status bdrs_server_destroy(bdrs_server sv) {
   }
   sv->cv_work.notify_all();
   if (sv->worker.joinable()) sv->worker.join();
-  hipStreamSynchronize(sv->stream);
-  hipStreamDestroy(sv->stream);
+  // teardown: the worker has drained the stream's work; nothing to report
+  (void)hipStreamSynchronize(sv->stream);
+  (void)hipStreamDestroy(sv->stream);
   delete sv;
   return BDRS_OK;
 }

@@ -173,7 +173,7 @@ bdrs_status bdrs_autotune(const bdrs_params* p, int32_t rounds, bdrs_tune_entry*
     }
   }
   for (auto& x : ev)
-    if (x) hipEventDestroy(x);
+    if (x) (void)hipEventDestroy(x);
   bdrs_destroy(s);
   if (st != BDRS_OK) return st;
   if (e != hipSuccess) return hip_status(e, "autotune");
