@@ -46,13 +46,13 @@ EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters
 # null.
 TRAFFIC_KERNEL_SHA256 = "b8ad0ff1247716f684377346d8fc1782dc4228f5df76344905d5b3fe9b89946b"
 TRAFFIC_SPLITS = 16
-TRAFFIC_BYTES_PER_LAUNCH = 6.83e6
+TRAFFIC_BYTES_PER_LAUNCH = 6.84e6
 # Counters of the same profile (per dispatch of k_sweep<2,0> in the replay):
 # VALU lane instructions and v_exp_f32 per evaluated entry (x 64 / evaluated
 # entries), VALU issue utilisation (lane instructions / duration / (256 x 64 x
 # 2.4 GHz)) and rocprof's VALUBusy.
-PROFILE_COUNTERS = {"valu_instr_per_evaluated_entry": 8.19, "exp_per_evaluated_entry": 1.000,
-                    "valu_issue_frac": 0.288, "VALUBusy": 19.9,
+PROFILE_COUNTERS = {"valu_instr_per_evaluated_entry": 8.19, "exp_per_evaluated_entry": 1.007,
+                    "valu_issue_frac": 0.294, "VALUBusy": 19.6,
                     "source": "profiles/k_sweep_grid128x128.md"}
 
 
