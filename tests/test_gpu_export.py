@@ -56,6 +56,9 @@ CASES = [
     ("rand_d3_obdrs", lambda: inputs.random_problem(300, 517, 3, 1), 0.5, 1.5, "dual_bdrs", 12),
     ("rand_d1_as", lambda: inputs.random_problem(257, 190, 1, 2), 0.5, 1.0, "annealed_sinkhorn", 20),
     ("rand_d2_tiny", lambda: inputs.random_problem(5, 70, 2, 3), 0.3, 1.0, "dual_bdrs", 3),
+    ("one_row", lambda: inputs.random_problem(1, 300, 3, 5), 0.5, 1.0, "dual_bdrs", 4),
+    ("one_col", lambda: inputs.random_problem(270, 1, 2, 6), 0.5, 1.5, "dual_bdrs", 4),
+    ("single", lambda: inputs.random_problem(1, 1, 1, 4), 0.5, 1.0, "dual_bdrs", 2),
 ]
 
 
@@ -128,6 +131,19 @@ def test_repaired_plan_matches_oracle(lam):
     assert tw.certificate()["repaired_cost"] == info["cost"]
     sv.close()
     tw.close()
+
+
+@pytest.mark.parametrize("m,n", [(1, 300), (270, 1), (1, 1)])
+def test_repaired_plan_degenerate_shapes(m, n):
+    """One source or one target point: the only feasible plan is r c^T, and
+    both exports return it."""
+    prob = inputs.random_problem(m, n, 2, 8)
+    sv = solver_for(prob, 0.5)
+    sv.step(5)
+    for kind in ("rounded", "repaired"):
+        P = np64(sv.plan_entries(sv.export_plan(kind)))
+        assert np.allclose(P, np.outer(prob.r, prob.c), rtol=3e-5, atol=0), kind
+    sv.close()
 
 
 def test_row_strips_equal_the_whole_and_iteration_unchanged():
