@@ -83,6 +83,30 @@ def test_sweep_parity_random_weights(name, make, eps):
         assert rel_err(got, ref) <= SWEEP_TOL, (name, eps, transpose, rel_err(got, ref))
 
 
+# sizes at and around the 64-point tile and the 256-output block, and a few
+# drawn at random (seeded): every ragged tail the layout can have
+BOUNDARY_SIZES = [(63, 64), (64, 65), (65, 255), (255, 256), (256, 257), (257, 129), (129, 511), (513, 63)]
+
+
+def ragged_cases():
+    rng = np.random.default_rng(2024)
+    cases = [(m, n, 1 + i % 3) for i, (m, n) in enumerate(BOUNDARY_SIZES)]
+    cases += [(int(rng.integers(1, 2500)), int(rng.integers(1, 2500)), int(rng.integers(1, 4))) for _ in range(8)]
+    return cases
+
+
+@pytest.mark.parametrize("m,n,d", ragged_cases())
+def test_sweep_parity_ragged_sizes(m, n, d):
+    prob = inputs.random_problem(m, n, d, m * 7 + n)
+    sv = solver_for(prob)
+    rng = np.random.default_rng(m + 31 * n)
+    for eps in (0.05, 2e-3):
+        for transpose in (False, True):
+            w = rng.normal(0.0, 10.0, prob.m if transpose else prob.n)
+            got, ref = sweep_both(sv, prob, w, eps, transpose)
+            assert rel_err(got, ref) <= SWEEP_TOL, (m, n, d, eps, transpose, rel_err(got, ref))
+
+
 def test_sweep_duplicate_points_and_masked_weights():
     rng = np.random.default_rng(3)
     x = np.repeat(rng.random((10, 2)).astype(np.float32), 13, axis=0)   # 130 points, 10 distinct
