@@ -44,7 +44,7 @@ EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters
 # holds for the kernel sources with this sha256 (of bdrs_kernels.hip followed
 # by bdrs_internal.h) and that split count only; otherwise it is reported as
 # null.
-TRAFFIC_KERNEL_SHA256 = "b8ad0ff1247716f684377346d8fc1782dc4228f5df76344905d5b3fe9b89946b"
+TRAFFIC_KERNEL_SHA256 = "237cbb8703d376621f0b7e214819cfc643498810db036812f95cf7b856330d05"
 TRAFFIC_SPLITS = 16
 TRAFFIC_BYTES_PER_LAUNCH = 6.84e6
 # Counters of the same profile (per dispatch of k_sweep<2,0> in the replay):

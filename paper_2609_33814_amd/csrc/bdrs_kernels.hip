@@ -1270,40 +1270,62 @@ __global__ void k_export_factors(LaunchCtx c, int repaired, const double* __rest
 
 // Dense rows [row_begin, row_begin + nrows) of a factored plan, row-major in
 // original order: out[(i - row_begin) n + j] = exp(u_i + v_j - kap |x_i - y_j|^2)
-// + a_i b_j, in float64 from the stored float32 coordinates.  One thread per
-// column holds y_j, v_j and b_j; a block walks kEntryRows rows at a time, the
-// row's point and factors being uniform across it.  Write-bound: 8 bytes per
-// entry.
-constexpr int kEntryRows = 8;
-template <int D>
+// (+ a_i b_j when R1), in float64 from the stored float32 coordinates.  One
+// thread per column holds y_j, v_j and b_j.  A block walks strips of
+// kEntryRows rows: its first wavefront loads the strip's slots, coordinates
+// and factors (one lane per row, two round trips per strip) into LDS, and
+// every thread then reads them from there for each row.  Write-bound: 8 bytes
+// per entry.
+constexpr int kEntryRows = 64;
+template <int D, bool R1>
 __global__ __launch_bounds__(kBlock) void k_plan_entries(LaunchCtx c, const double* __restrict__ u,
                                                          const double* __restrict__ v,
                                                          const double* __restrict__ a,
                                                          const double* __restrict__ b, double kap,
                                                          long long row_begin, long long nrows,
                                                          double* __restrict__ out) {
+  __shared__ float sx[D][kEntryRows];
+  __shared__ double su[kEntryRows], sa[kEntryRows];
   const int n = c.cols.count;
   const int j = blockIdx.y * kBlock + threadIdx.x;
-  if (j >= n) return;
-  const int qj = c.cols.iperm[j];
+  const bool col = j < n;  // no early return: every thread reaches the barriers
   double y[D];
-  for (int d = 0; d < D; ++d) y[d] = (double)c.cols.abs[(size_t)d * c.cols.np + qj];
-  const double vj = v[j];
-  const double bj = b ? b[j] : 0.0;
+  double vj = 0.0, bj = 0.0;
+  if (col) {
+    const int qj = c.cols.iperm[j];
+#pragma unroll
+    for (int d = 0; d < D; ++d) y[d] = (double)c.cols.abs[(size_t)d * c.cols.np + qj];
+    vj = v[j];
+    bj = R1 ? b[j] : 0.0;
+  } else {
+#pragma unroll
+    for (int d = 0; d < D; ++d) y[d] = 0.0;
+  }
   const long long blocks = (nrows + kEntryRows - 1) / kEntryRows;
+  const long long last = row_begin + nrows - 1;
   for (long long rb = blockIdx.x; rb < blocks; rb += gridDim.x) {
     const long long r0 = rb * kEntryRows;
     const int rows = (int)min((long long)kEntryRows, nrows - r0);
+    __syncthreads();  // the previous strip's rows have been read
+    if (threadIdx.x < kEntryRows) {
+      const long long i = min(row_begin + r0 + threadIdx.x, last);
+      const int q = c.rows.iperm[i];
+#pragma unroll
+      for (int d = 0; d < D; ++d) sx[d][threadIdx.x] = c.rows.abs[(size_t)d * c.rows.np + q];
+      su[threadIdx.x] = u[i];
+      sa[threadIdx.x] = R1 ? a[i] : 0.0;
+    }
+    __syncthreads();
+    if (!col) continue;
+    double* o = out + (size_t)r0 * n + j;
     for (int t = 0; t < rows; ++t) {
-      const long long i = row_begin + r0 + t;
-      const int qi = c.rows.iperm[i];
       double d2 = 0.0;
+#pragma unroll
       for (int d = 0; d < D; ++d) {
-        const double e = (double)c.rows.abs[(size_t)d * c.rows.np + qi] - y[d];
+        const double e = (double)sx[d][t] - y[d];
         d2 = fma(e, e, d2);
       }
-      const double ai = a ? a[i] : 0.0;
-      out[(size_t)(r0 + t) * n + j] = exp(u[i] + vj - kap * d2) + ai * bj;
+      o[(size_t)t * n] = exp(su[t] + vj - kap * d2) + sa[t] * bj;
     }
   }
 }
@@ -1500,13 +1522,17 @@ hipError_t launch_plan_entries(const LaunchCtx& c, const double* u, const double
   if (nrows <= 0 || c.cols.count <= 0) return hipSuccess;
   const long long rblocks = (nrows + kEntryRows - 1) / kEntryRows;
   const dim3 grid((unsigned)std::min(rblocks, 65536LL), (unsigned)((c.cols.count + kBlock - 1) / kBlock));
-#define BDRS_ENTRIES(DD)                                                                                 \
-  hipLaunchKernelGGL(k_plan_entries<DD>, grid, dim3(kBlock), 0, c.stream, c, u, v, a, b, kap, row_begin, \
-                     nrows, out)
-  switch (c.dim) {
-    case 1: BDRS_ENTRIES(1); break;
-    case 2: BDRS_ENTRIES(2); break;
-    default: BDRS_ENTRIES(3); break;
+#define BDRS_ENTRIES(DD, RR)                                                                        \
+  hipLaunchKernelGGL((k_plan_entries<DD, RR>), grid, dim3(kBlock), 0, c.stream, c, u, v, a, b, kap, \
+                     row_begin, nrows, out)
+  const bool r1 = a != nullptr && b != nullptr;
+  switch (c.dim * 2 + (r1 ? 1 : 0)) {
+    case 2: BDRS_ENTRIES(1, false); break;
+    case 3: BDRS_ENTRIES(1, true); break;
+    case 4: BDRS_ENTRIES(2, false); break;
+    case 5: BDRS_ENTRIES(2, true); break;
+    case 6: BDRS_ENTRIES(3, false); break;
+    default: BDRS_ENTRIES(3, true); break;
   }
 #undef BDRS_ENTRIES
   return hipGetLastError();
