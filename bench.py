@@ -11,7 +11,8 @@ steps with the inputs resident in HBM.  Printed: one JSON line.
 
 Also reported: the dominant kernel's roofline fraction (sweep durations from
 HIP events recorded by the library on its own stream), the time to a 1%
-relative duality gap for plain BDRS (lambda = 1) and O-BDRS (lambda = 1.99),
+relative duality gap for plain BDRS (lambda = 1) and O-BDRS (lambda = 1.2,
+1.5, 1.99),
 and the FP64 oracle timed on the host on a bounded sample of the same sweeps.
 """
 from __future__ import annotations
@@ -621,7 +622,7 @@ def main() -> int:
 
     ttg = {}
     if not args.no_ttg:
-        for lam in (1.0, 1.99):
+        for lam in (1.0, 1.2, 1.5, 1.99):
             s2 = bdrs.Solver(X, Y, R, C, prob.cost_scale, eta=ETA, lam=lam)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
