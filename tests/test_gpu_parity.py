@@ -312,6 +312,32 @@ def test_full_size_colour_sampled_rows():
             assert rel_err(got, ref) <= SWEEP_TOL, (transpose, eps)
 
 
+def test_full_size_fused_certificate():
+    """The certificate the solver fuses into its column sweep, in the
+    benchmark's launch configuration (128x128 grids, eta = 0.1, captured
+    50-iteration blocks, tuned splits, tiles skipped), against Prop. 3 /
+    Algorithm 2 evaluated by the oracle over all 2.7e8 entries from the
+    solver's own state at k = 299 (tolerances as for an identical state)."""
+    prob = inputs.c2_problem()
+    eta = 0.1
+    sv = solver_for(prob, eta=eta)
+    _, ce = sv.solve(0.0, 300, 50)
+    gs = sv.get_state()
+    assert ce["k"] == 299 and gs["k"] == 300
+    eps = alg1.schedule(eta, 1.0, 299)
+    npy = lambda key: gs[key].cpu().numpy()
+    ref = certificate.certificate(prob.x, prob.y, prob.cost_scale, prob.r, prob.c, npy("lah"), npy("lbh"),
+                                  npy("lt"), eps)
+    print("full-size fused certificate: dL", abs(ce["L"] - ref["L"]) / abs(ref["L"]),
+          "dU", abs(ce["U"] - ref["U"]) / ref["U"], "ddelta", abs(ce["delta"] - ref["delta"]),
+          "rel gap", ce["rel_gap"], ref["rel"])
+    assert abs(ce["L"] - ref["L"]) <= 1e-9 * abs(ref["L"])
+    assert abs(ce["U"] - ref["U"]) <= 1e-5 * abs(ref["U"])
+    assert abs(ce["delta"] - ref["delta"]) <= 1e-4 * ref["delta"] + 2e-6
+    assert abs(ce["rel_gap"] - ref["rel"]) <= 1e-3 * abs(ref["rel"])
+    assert ce["n_nonfinite"] == 0
+
+
 def test_skipped_tiles_late_in_a_solve():
     """Late in a solve most input tiles lie far below each output's running
     maximum and are skipped; the sweeps the solver ran there (with its own
