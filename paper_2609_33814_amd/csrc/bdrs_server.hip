@@ -10,6 +10,7 @@
 // pool memory is reused by the next admissions).  The per-request arithmetic
 // is the single-problem one, so results do not depend on the mix.
 #include "bdrs_host.h"
+#include "bdrs_sched.h"
 
 #include <chrono>
 #include <cmath>
@@ -26,55 +27,7 @@ using namespace bdrs_host;
 
 namespace {
 
-// First-fit allocator over [0, size) in 256-byte units (host bookkeeping only).
-class PoolAlloc {
- public:
-  explicit PoolAlloc(size_t size) : size_(size) { free_[0] = size; }
-  bool alloc(size_t bytes, size_t* off) {
-    bytes = align_up(bytes ? bytes : 1);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        *off = it->first;
-        const size_t rest = it->second - bytes;
-        const size_t at = it->first + bytes;
-        free_.erase(it);
-        if (rest) free_[at] = rest;
-        used_ += bytes;
-        sizes_[*off] = bytes;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off) {
-    auto s = sizes_.find(off);
-    if (s == sizes_.end()) return;
-    size_t bytes = s->second;
-    sizes_.erase(s);
-    used_ -= bytes;
-    auto next = free_.lower_bound(off);
-    if (next != free_.end() && off + bytes == next->first) {
-      bytes += next->second;
-      free_.erase(next);
-    }
-    auto it = free_.lower_bound(off);
-    if (it != free_.begin()) {
-      auto prev = std::prev(it);
-      if (prev->first + prev->second == off) {
-        prev->second += bytes;
-        return;
-      }
-    }
-    free_[off] = bytes;
-  }
-  size_t used() const { return used_; }
-  size_t size() const { return size_; }
-
- private:
-  size_t size_, used_ = 0;
-  std::map<size_t, size_t> free_;    // offset -> bytes
-  std::map<size_t, size_t> sizes_;   // allocated offset -> bytes
-};
+using bdrs_sched::PoolAlloc;
 
 struct Request {
   uint64_t ticket = 0;
@@ -154,13 +107,13 @@ void bdrs_server_::run() {
     // are free; with the size-aware policy a large request waits while another
     // large one runs and the requests behind it that are small may pass it
     bool changed = false;
-    while (!stop && !queue.empty() && (int)running.size() < max_slots) {
-      bool big_running = false;
-      if (big_work > 0)
-        for (auto& r : running) big_running = big_running || r->work > big_work;
-      auto pick = queue.begin();
-      while (pick != queue.end() && big_work > 0 && big_running && (*pick)->work > big_work) ++pick;
-      if (pick == queue.end()) break;
+    while (!stop && !queue.empty()) {
+      std::vector<double> queued_work, running_work;
+      for (auto& r : queue) queued_work.push_back(r->work);
+      for (auto& r : running) running_work.push_back(r->work);
+      const int pi = bdrs_sched::pick_admission(queued_work, running_work, max_slots, big_work);
+      if (pi < 0) break;
+      auto pick = queue.begin() + pi;
       std::shared_ptr<Request> rq = *pick;
       if (!dev_ok) {
         queue.erase(pick);
