@@ -338,6 +338,41 @@ def test_full_size_fused_certificate():
     assert ce["n_nonfinite"] == 0
 
 
+@pytest.mark.parametrize("side,iters", [(32, 500), (128, 300)])
+def test_dual_feasibility_max_sweep(side, iters):
+    """f_i + g_j <= C_ij for every pair (Prop. 3; g is the soft c-transform of
+    f), with f = eps log alpha-hat and g = eps (log beta-hat - log c) of the
+    solver's last certified iteration, checked over all m n pairs by the GPU's
+    own sweep used as a max-sweep: at temperature eps' the LSE of
+    (g_j - C_ij) / eps' lies between max_j (g_j - C_ij) / eps' and that plus
+    log n.  Sampled rows take the exact maximum from the oracle's cost."""
+    prob = inputs.grid_problem(side, 21, 22)
+    eta = 0.1
+    sv = solver_for(prob, eta=eta)
+    sv.step(iters)
+    gs = sv.get_state()
+    eps = alg1.schedule(eta, 1.0, iters - 1)
+    f = eps * gs["lah"].cpu().numpy()
+    g = eps * (gs["lbh"].cpu().numpy() - np.log(prob.c))
+    eps1 = 1e-6
+    out = sv.lse(torch.as_tensor(g / eps1, device=dev()), eps1).cpu().numpy()
+    viol = f + eps1 * out                  # >= max_j (f_i + g_j - C_ij) for every row i
+    # the float32 sweep's error on g (a relative 1e-5 per LSE at the solver's eps)
+    tol = eps1 * np.log(prob.n) + 1e-5 * eps * float(np.max(np.abs(gs["lbh"].cpu().numpy())))
+    print(f"side {side}: max_i max_j (f_i + g_j - C_ij) <= {viol.max():.3e} (tolerance {tol:.1e})")
+    assert viol.max() <= tol, (viol.max(), tol)
+    rng = np.random.default_rng(41)
+    rows = rng.choice(prob.m, 64, replace=False)
+    C = lse.cost_block(prob.x[rows], prob.y, prob.cost_scale)
+    exact = (f[rows, None] + g[None, :] - C).max(axis=1)
+    assert np.all(exact <= tol)
+    # the max-sweep bounds the exact maximum from above, up to its own float32
+    # error (the per-sweep bar, relative to the LSE's magnitude, times eps')
+    sweep_err = eps1 * SWEEP_TOL * np.maximum(1.0, np.abs(out[rows]))
+    print(f"side {side}: max-sweep minus exact max over sampled rows >= {(viol[rows] - exact).min():.3e}")
+    assert np.all(viol[rows] >= exact - sweep_err)
+
+
 def test_skipped_tiles_late_in_a_solve():
     """Late in a solve most input tiles lie far below each output's running
     maximum and are skipped; the sweeps the solver ran there (with its own
