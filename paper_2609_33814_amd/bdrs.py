@@ -288,6 +288,29 @@ class Solver:
                                     int(cert_every), ctypes.byref(ce)), allow=(OK, NOT_CONVERGED))
         return st == OK, ce.as_dict()
 
+    def solve_logged(self, tau: float, max_iters: int, cert_every: int, path: str, relative: bool = True):
+        """bdrs_solve one certificate block at a time, appending one JSON line per
+        certificate to `path` (k, eps, L, U, gap, rel_gap, the best bounds, delta,
+        cost_Z, n_nonfinite and the wall-clock seconds since the call).  The
+        iterates and certificates are those of solve(tau, max_iters, cert_every)
+        from the same state; returns the same (reached, certificate)."""
+        import json
+        import time
+        t0 = time.perf_counter()
+        done, ok, ce = 0, False, None
+        keys = ("k", "eps", "L", "U", "gap", "rel_gap", "L_best", "U_best", "rel_gap_best", "k_L_best",
+                "k_U_best", "delta", "cost_Z", "n_nonfinite")
+        with open(path, "a") as log:
+            while done < max_iters and not ok:
+                block = min(cert_every, max_iters - done)
+                ok, ce = self.solve(tau, block, cert_every, relative)
+                done += block
+                rec = {key: ce[key] for key in keys}
+                rec["t_wall"] = round(time.perf_counter() - t0, 6)
+                log.write(json.dumps(rec) + "\n")
+                log.flush()
+        return ok, ce
+
     def restore_best(self) -> int:
         """Makes the retained lowest-gap state current (keep_best=True); returns its iteration count."""
         k = ctypes.c_int64()

@@ -89,3 +89,31 @@ def test_solve_block_graphs_match_eager_solve(lam, every):
     assert a[4]["k"] == b[4]["k"]
     for key in ("row", "col"):
         assert torch.equal(a[5][key], b[5][key]), key
+
+
+def test_solve_logged_records_every_certificate(tmp_path):
+    """solve_logged writes one JSON line per certificate and ends where one
+    solve call ends, bit for bit."""
+    import json
+    from paper_2609_33814_amd import bdrs, inputs
+    prob = inputs.grid_problem(32, 11, 12)
+    d = torch.device("cuda:0")
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=d)
+    mk = lambda: bdrs.Solver(t(prob.x, torch.float32), t(prob.y, torch.float32), t(prob.r, torch.float64),
+                             t(prob.c, torch.float64), prob.cost_scale, eta=0.1)
+    a, b = mk(), mk()
+    path = str(tmp_path / "certs.jsonl")
+    ok_a, ce_a = a.solve_logged(0.01, 5000, 50, path)
+    ok_b, ce_b = b.solve(0.01, 5000, 50)
+    assert ok_a and ok_b
+    recs = [json.loads(line) for line in open(path)]
+    assert [r["k"] for r in recs] == list(range(49, ce_b["k"] + 1, 50))
+    assert all(x["rel_gap_best"] >= y["rel_gap_best"] for x, y in zip(recs, recs[1:]))
+    assert all(x["t_wall"] <= y["t_wall"] for x, y in zip(recs, recs[1:]))
+    for key in ("k", "L", "U", "rel_gap", "L_best", "U_best", "rel_gap_best", "delta"):
+        assert ce_a[key] == ce_b[key] == recs[-1][key], key
+    sa, sb = a.get_state(), b.get_state()
+    for key in ("la", "lb", "lah"):
+        assert torch.equal(sa[key], sb[key]), key
+    a.close()
+    b.close()
