@@ -47,7 +47,7 @@ typedef enum {
   BDRS_E_NOMEM = -2,       /* workspace too small / admission over the memory budget  */
   BDRS_E_DEVICE = -3,      /* HIP error, or no usable gfx950 device                   */
   BDRS_E_STATE = -4,       /* call not valid in the object's current state            */
-  BDRS_E_NUMERIC = -5      /* non-finite values in the dual state or the certificate  */
+  BDRS_E_NUMERIC = -5      /* non-finite values, or a negative duality gap (U < L)    */
 } bdrs_status;
 
 /* flags */
@@ -94,8 +94,11 @@ typedef struct bdrs_solver_* bdrs_solver;
  *   cost_scale s > 0 in C_ij = s ||x_i - y_j||^2
  *   eta        initial temperature eta > 0 (Algorithm 1: eta_k = eta / (lambda k + 1))
  *   lambda     overrelaxation, 1 <= lambda < 2 (Prop. 2; 1 = BDRS)
- *   omega      Omega >= osc(C) used by the upper bound U (Prop. 3); 1 is valid
- *              whenever the costs lie in [0, 1]
+ *   omega      Omega >= osc(C) used by the upper bound U (Prop. 3), finite and
+ *              > 0; 1 is valid whenever the costs lie in [0, 1].  The library
+ *              cannot check Omega >= osc(C) in O(m + n); a too small Omega can
+ *              make U fall below L, which every certificate reports
+ *              (bdrs_cert.negative_gap, BDRS_E_NUMERIC)
  *   workspace  device memory of at least bdrs_workspace_size() bytes, 256-byte
  *              aligned, owned by the caller, used exclusively by this solver
  *              until bdrs_destroy
@@ -131,6 +134,15 @@ typedef struct {
  *   cost_Z       <C, Z> = sum_j s_j mu_j, the cost of the intermediate plan
  *   repaired_cost <C, Z^> of the feasible repair (only with BDRS_F_REPAIR, else NaN)
  *   n_nonfinite  number of non-finite values met in the certificate inputs
+ *   negative_gap 1 when U - L < -1e-9 |U| for this certificate, or
+ *                U_best - L_best < -1e-9 |U_best| for the best bounds, else 0.
+ *                Prop. 3 gives L <= p* <= U for every certificate, so a
+ *                negative gap means the bounds are not valid (float32 error
+ *                in the sweeps, or omega below osc(C)).  The gap is reported
+ *                as computed, never clamped; the call returns BDRS_E_NUMERIC,
+ *                the stopping rule never counts such a certificate as meeting
+ *                its target, and a certificate whose own gap is negative is
+ *                not folded into the best bounds.
  */
 typedef struct {
   int64_t k;
@@ -139,6 +151,7 @@ typedef struct {
   int64_t k_L_best, k_U_best;
   double delta, cost_Z, repaired_cost;
   int64_t n_nonfinite;
+  int64_t negative_gap;
 } bdrs_cert;
 
 /* Bytes of device workspace bdrs_create needs for these sizes (O(m + n)).
@@ -164,7 +177,8 @@ BDRS_API bdrs_status bdrs_step(bdrs_solver s, int32_t iters);
  * extra column pass from the stored log alpha-hat and log beta-tilde, then
  * the float64 reductions.  With BDRS_F_REPAIR one more row pass gives the
  * repaired cost.  Updates the best bounds.  Synchronous.  BDRS_E_STATE if no
- * iteration has run yet. */
+ * iteration has run yet; BDRS_E_NUMERIC (with *out filled) for non-finite
+ * values or a negative gap (bdrs_cert.negative_gap). */
 BDRS_API bdrs_status bdrs_certificate(bdrs_solver s, bdrs_cert *out);
 
 /* Runs until (U_best - L_best) / U_best <= tau (tau_relative != 0) or
@@ -172,7 +186,9 @@ BDRS_API bdrs_status bdrs_certificate(bdrs_solver s, bdrs_cert *out);
  * iteration k with (k + 1) % cert_every == 0 and after the last; the
  * certificate is fused into that iteration's column sweep.  At most
  * max_iters iterations.  *out holds the last certificate.  Returns BDRS_OK
- * when the target is met, BDRS_NOT_CONVERGED at the cap.
+ * when the target is met, BDRS_NOT_CONVERGED at the cap, BDRS_E_NUMERIC at
+ * the first certificate with non-finite values or a negative gap (a
+ * negative gap never meets the target).
  * A block of cert_every iterations that starts at a multiple of cert_every
  * and ends with its certificate is captured once as a hipGraph (on a private
  * stream of the solver; the kernels read the iteration counter from device
@@ -376,14 +392,17 @@ BDRS_API bdrs_status bdrs_batch_solve(const bdrs_solver *solvers, int32_t count,
  * Solve server: continuous batching of independent OT solves on one GPU.
  * The server owns a device memory pool given by the caller (the "HBM
  * budget"); every admitted request gets its workspace (bdrs_workspace_size of
- * its sizes) from the pool.  A worker thread admits queued requests in
- * arrival order whenever a slot and pool memory are free, runs blocks of
- * block_iters iterations of all running requests together (one launch per
- * phase, as in bdrs_batch_solve), evaluates each request's certificate at
- * the end of every block, and retires a request when its stopping rule holds
- * (same rule as bdrs_solve with cert_every = block_iters) or max_iters is
- * reached, releasing its memory for the next request.  A request's result is
- * bitwise the same as solving it alone with bdrs_solve.
+ * its sizes) from the pool, and the batch engine's descriptors and work lists
+ * for the running set live there too (a request is admitted only when both
+ * fit).  A worker thread admits queued requests in arrival order whenever a
+ * slot and pool memory are free, runs blocks of block_iters iterations of all
+ * running requests together (one launch per phase, as in bdrs_batch_solve;
+ * a block whose running set equals the previous block's is captured as a
+ * hipGraph and replayed until the set changes), evaluates each request's
+ * certificate at the end of every block, and retires a request when its
+ * stopping rule holds (same rule as bdrs_solve with cert_every = block_iters)
+ * or max_iters is reached, releasing its memory for the next request.  A
+ * request's result is bitwise the same as solving it alone with bdrs_solve.
  */
 typedef struct bdrs_server_* bdrs_server;
 
@@ -410,7 +429,11 @@ typedef struct {
  * block_iters >= 1 iterations per block.  Starts the worker thread. */
 BDRS_API bdrs_status bdrs_server_create(void *pool, size_t pool_bytes, int32_t max_slots,
                                         int32_t block_iters, bdrs_server *out);
-/* Validates and copies a request; thread-safe.  BDRS_E_NOMEM if its
+/* Validates a request (sizes, parameters, and the contents of its arrays as
+ * in bdrs_create) and prepares its host image (points in tile order, tile
+ * records) on the calling thread, so that the worker only uploads it at
+ * admission; the request's latency (t_submit) starts when this call starts.
+ * Thread-safe.  BDRS_E_INVALID for a bad request, BDRS_E_NOMEM if its
  * workspace can never fit the pool.  *ticket identifies the request. */
 BDRS_API bdrs_status bdrs_server_submit(bdrs_server s, const bdrs_request *req, uint64_t *ticket);
 /* Admission policy (thread-safe; takes effect at the next block boundary).

@@ -1,34 +1,35 @@
-"""Algorithm 1 (Dual O-BDRS, log domain), step by step in FP64.
+"""Dual O-BDRS (Algorithm 1) in the log domain, in FP64.
 
 Test infrastructure only (see the package docstring).
 
-Notation follows Algorithm 1 and Proposition 2 in natural-log form:
-``la`` = log alpha^k, ``lah`` = log alpha-hat^k, ``lb`` = log beta^k,
-``lbh`` = log beta-hat^k, ``lt`` = log beta-tilde^{k-1}.  lambda = 1 is Dual
-BDRS (Prop. 1; alpha = alpha-hat = a, beta = beta-hat = b).
+What the method computes, in terms of Prop. 2: two scaling vectors, alpha
+for the rows and beta for the columns, kept as natural logarithms.  Each
+iteration k works at the temperature eta_k = eta / (lambda k + 1), i.e. with
+the kernel exp(-C / eta_k).  It first extrapolates the column scaling along
+its last change (momentum: beta^{k-1} moved on by 1/lambda of its step from
+beta^{k-2}); then it makes the row scaling exact for the row marginal r
+against that extrapolated column scaling, and the column scaling exact for
+the column marginal c against the new (unrelaxed) row scaling.  The
+overrelaxation mixes each unrelaxed scaling with the previous relaxed one,
+weight lambda on the new one (a geometric mix in the linear domain); the
+unrelaxed ones carry a hat.  With lambda = 1 there is no mixing and no hat:
+Dual BDRS (Prop. 1).  All three scalings start at one (zero in the log).
 
-Initialisation: log alpha^{-1} = log beta^{-2} = log beta^{-1} = 0.
-Iteration k:
-  eps_k   = eta / (lambda k + 1)
-  lt      = lb1 + (lb1 - lb2) / lambda          (lb1 = log beta^{k-1}, lb2 = log beta^{k-2})
-  lah     = log r - LSE_j(lt_j - C_ij / eps_k)
-  la      = (1 - lambda) la_prev + lambda lah
-  lbh     = log c - LSE_i(lah_i - C_ij / eps_k)  (the column update uses alpha-hat)
-  lb      = (1 - lambda) lb1 + lambda lbh
-then, when requested, the certificate of Prop. 3 from (lah, lbh, lt, eps_k).
-
-The state also keeps log beta^{k-1}: the next extrapolation needs both
-beta^k and beta^{k-1}, and the tuple Algorithm 1 returns lacks it.
+Names: ``la`` = log alpha^k, ``lah`` = log alpha-hat^k, ``lb`` = log beta^k,
+``lbh`` = log beta-hat^k, ``lt`` = log beta-tilde^{k-1} (the extrapolated
+column scaling the row update of iteration k reads).  The state also keeps
+log beta^{k-1}: the next extrapolation needs both beta^k and beta^{k-1},
+which the tuple the algorithm returns does not hold.
 
 Ablation variants (lambda = 1; the controlled ablation of the appendix and
 Cor. 1, which names the two changes that turn annealed Sinkhorn into Dual
-BDRS).  All share the column update at eps_k = eta / (k + 1), i.e. the
-kernel K^{.(k+1)}, the schedule and the initialisation; the row update is
+BDRS).  All share the column update at eta_k = eta / (k + 1), the schedule
+and the initialisation, and differ in the row update:
 
   log a^k = [theta_k log a^{k-1}] + log r - LSE_j(log t_j - C_ij / eps_row)
 
 with OLD_KERNEL: eps_row = eta / k (the kernel K^{.k}; K^{.0} is all ones,
-eps_row = inf) instead of eps_k; NO_MOMENTUM: t = b^{k-1} instead of the
+eps_row = inf) instead of eta_k; NO_MOMENTUM: t = b^{k-1} instead of the
 extrapolated b~^{k-1}; DEBIASED (with both of the former, the debiased
 annealed Sinkhorn): the bracketed factor with theta_k = 0 for k <= 1 and
 1 / k for k >= 2 (the first iteration that has a previous row scaling uses
@@ -91,14 +92,16 @@ def momentum(lb1, lb2, lam):
     return lb1 + (lb1 - lb2) / lam
 
 
-def row_update(prob, lt, eps):
+def row_update(prob, lt, eps, perturb=None):
     """log alpha-hat^k = log r - LSE_j(log beta-tilde_j - C_ij / eps_k)."""
-    return np.log(prob.r) - implicit_lse(prob.x, prob.y, prob.cost_scale, eps, lt)
+    out = implicit_lse(prob.x, prob.y, prob.cost_scale, eps, lt)
+    return np.log(prob.r) - (out if perturb is None else perturb(out))
 
 
-def col_update(prob, lah, eps):
+def col_update(prob, lah, eps, perturb=None):
     """log beta-hat^k = log c - LSE_i(log alpha-hat_i - C_ij / eps_k)."""
-    return np.log(prob.c) - implicit_lse(prob.y, prob.x, prob.cost_scale, eps, lah)
+    out = implicit_lse(prob.y, prob.x, prob.cost_scale, eps, lah)
+    return np.log(prob.c) - (out if perturb is None else perturb(out))
 
 
 def column_weights(st: "State", variant: int = 0):
@@ -106,20 +109,24 @@ def column_weights(st: "State", variant: int = 0):
     return st.la if variant & DEBIASED else st.lah
 
 
-def iterate(prob, st: State, eta: float, lam: float, variant: int = 0) -> State:
-    """One iteration of Algorithm 1 (or of an ablation variant); returns the new state."""
+def iterate(prob, st: State, eta: float, lam: float, variant: int = 0, perturb=None) -> State:
+    """One iteration of Algorithm 1 (or of an ablation variant); returns the new state.
+
+    perturb (tests only): a map applied to every LSE result, e.g. rounding to
+    float32, to measure how far a given rounding of the sweeps moves the
+    trajectory; None leaves the FP64 arithmetic untouched."""
     k = st.k
     eps = schedule(eta, lam, k)
     eps_row = row_temperature(eta, lam, k, variant)
     lt = st.lb1.copy() if variant & NO_MOMENTUM else momentum(st.lb1, st.lb2, lam)
-    lah = row_update(prob, lt, eps_row)
+    lah = row_update(prob, lt, eps_row, perturb)
     if variant & DEBIASED:
         la = debias_theta(k) * st.la + lah
         colw = la
     else:
         la = (1.0 - lam) * st.la + lam * lah
         colw = lah
-    lbh = col_update(prob, colw, eps)
+    lbh = col_update(prob, colw, eps, perturb)
     lb = (1.0 - lam) * st.lb1 + lam * lbh
     return State(la=la, lb1=lb, lb2=st.lb1.copy(), lah=lah, lbh=lbh, lt=lt, k=k + 1)
 
@@ -131,7 +138,7 @@ def cert_due(k: int, cert_every: int, last: int) -> bool:
 
 def run(prob, eta: float, lam: float, iters: int, cert_every: int = 0,
         omega: float = 1.0, tau_rel: float | None = None, state: State | None = None,
-        keep_states: bool = False, variant: int = 0):
+        keep_states: bool = False, variant: int = 0, perturb=None):
     """Run Algorithm 1 for up to ``iters`` iterations.
 
     Returns (state, certs, states): certs is a list of dicts (iteration k, the
@@ -151,7 +158,7 @@ def run(prob, eta: float, lam: float, iters: int, cert_every: int = 0,
     k_end = st.k + iters - 1
     for _ in range(iters):
         k = st.k
-        st = iterate(prob, st, eta, lam, variant)
+        st = iterate(prob, st, eta, lam, variant, perturb)
         if keep_states:
             states.append(st.copy())
         if cert_due(k, cert_every, k_end):

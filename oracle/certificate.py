@@ -2,26 +2,35 @@
 
 Test infrastructure only (see the package docstring).
 
-Inputs are the scalings of the table in Sec. 3.4 ("Scalings shared by both
-methods"): A = alpha-hat^k (a^k for BDRS), B = beta-hat^k (b^k), t =
-beta-tilde^{k-1}, eps = eta / (lambda k + 1), all in natural-log form here.
+Inputs are the scalings the iteration has at hand (table of Sec. 3.4): the
+unrelaxed row scaling A, the unrelaxed column scaling B, the column scaling t
+the row update read, and that update's temperature eps, all in natural-log
+form here.  They satisfy the two normalisations A = r / (K t) and
+B = c / (K^T A) with K = exp(-C / eps).
 
-* dual potentials f = eps log A, g = eps log(B / c)   (Prop. 3, Eq. for f, g)
-* lower bound     L = <r, f> + <c, g>                  (Prop. 3)
-* per column j (Algorithm 2): l_ij = log A_i - C_ij / eps, M_j = max_i l_ij,
-  D_j = sum_i exp(l_ij - M_j), N_j = sum_i C_ij exp(l_ij - M_j),
-  mu_j = N_j / D_j, d_j = M_j + log D_j, s_j = exp(log t_j + d_j)
-* delta = 1/2 ||s - c||_1, U = sum_j s_j mu_j + Omega delta (Algorithm 2)
-* relative gap (U - L) / U (experiments, "relative duality gap").
+* Lower bound: the potentials f = eps log A and g = eps log(B / c) form a
+  feasible pair of the Kantorovich dual (g is the soft c-transform of f), so
+  L = <r, f> + <c, g> <= p*.
+* Upper bound: the plan Z = diag(A) K diag(t) has row sums r by the first
+  normalisation; its column sums are s = c t / B.  Its cost plus Omega
+  times the column mass that must move, delta = 1/2 ||s - c||_1, bounds the
+  cost of a feasible repair of Z, hence p*: U = <C, Z> + Omega delta.
+* Evaluation column by column (Algorithm 2): with the log terms
+  l_ij = log A_i - C_ij / eps of column j, shifted by the column's largest
+  one so that no exponential overflows or underflows to zero for the
+  leading terms (App. E), the shifted mass D_j and shifted cost-weighted
+  mass N_j give the mean cost mu_j = N_j / D_j of Z's column and the log of
+  its mass, log s_j = log t_j + max_i l_ij + log D_j; then <C, Z> =
+  sum_j s_j mu_j.
+* Relative gap (U - L) / U (experiments, "relative duality gap").
 
-The upper bound only needs a plan Z = diag(A) K_eps diag(t) whose row sums
-are r, i.e. A = r / (K_eps t) (the proof of Prop. 3 uses nothing else), and
-the lower bound only a dual feasible pair: g is the soft c-transform of f at
-the temperature of the column update.  The ablation variants, whose row and
-column updates use different temperatures (or whose column update reads a
-debiased row scaling), therefore take U from the row update (A, t, eps) and
-L from the column update (its row scaling ``colw`` and temperature
-``eps_col``); for Algorithm 1 both coincide.
+The upper bound only needs a plan whose row sums are r, i.e. A = r / (K t)
+(the proof of Prop. 3 uses nothing else), and the lower bound only a dual
+feasible pair.  The ablation variants, whose row and column updates use
+different temperatures (or whose column update reads a debiased row
+scaling), therefore take U from the row update (A, t, eps) and L from the
+column update (its row scaling ``colw`` and temperature ``eps_col``); for
+Algorithm 1 both coincide.
 """
 from __future__ import annotations
 
@@ -32,14 +41,26 @@ from .lse import cost_block
 TILE = 256
 
 
-def column_statistics(x, y, s, eps, lah, cols=None):
+def column_statistics(x, y, s, eps, lah, cols=None, workers: int = 1):
     """(M_j, D_j, N_j) of Algorithm 2 for every column j (or the listed ones).
 
     Columns of the implicit cost are rows of the transposed cost, so the loop
     runs over blocks of target points y_j against all source points x_i.
+    With workers > 1 the columns are split into chunks (multiples of the
+    block size) evaluated by that many threads (NumPy releases the
+    interpreter lock inside its array operations); every column's
+    arithmetic is the same, so the result is identical.
     """
     lah = np.asarray(lah, dtype=np.float64)
     idx = np.arange(y.shape[0]) if cols is None else np.asarray(cols)
+    if workers > 1 and idx.shape[0] > TILE:
+        from concurrent.futures import ThreadPoolExecutor
+        per = -(-idx.shape[0] // workers)
+        per = -(-per // TILE) * TILE
+        chunks = [idx[a:a + per] for a in range(0, idx.shape[0], per)]
+        with ThreadPoolExecutor(len(chunks)) as ex:
+            parts = list(ex.map(lambda c: column_statistics(x, y, s, eps, lah, c), chunks))
+        return tuple(np.concatenate([p[i] for p in parts]) for i in range(3))
     M = np.empty(idx.shape[0])
     D = np.empty(idx.shape[0])
     N = np.empty(idx.shape[0])
@@ -62,10 +83,10 @@ def lower_bound(r, c, lah, lbh, eps):
     return float(np.dot(r, f) + np.dot(c, g)), f, g
 
 
-def certificate(x, y, s, r, c, lah, lbh, lt, eps, omega=1.0, colw=None, eps_col=None):
+def certificate(x, y, s, r, c, lah, lbh, lt, eps, omega=1.0, colw=None, eps_col=None, workers: int = 1):
     """All quantities of Proposition 3 / Algorithm 2 for one iteration."""
     L, f, g = lower_bound(r, c, lah if colw is None else colw, lbh, eps if eps_col is None else eps_col)
-    M, D, N = column_statistics(x, y, s, eps, lah)
+    M, D, N = column_statistics(x, y, s, eps, lah, workers=workers)
     mu = N / D
     d = M + np.log(D)
     log_s = np.asarray(lt, dtype=np.float64) + d

@@ -68,7 +68,7 @@ class Cert(ctypes.Structure):
         ("rel_gap_best", ctypes.c_double), ("k_L_best", ctypes.c_int64),
         ("k_U_best", ctypes.c_int64), ("delta", ctypes.c_double),
         ("cost_Z", ctypes.c_double), ("repaired_cost", ctypes.c_double),
-        ("n_nonfinite", ctypes.c_int64),
+        ("n_nonfinite", ctypes.c_int64), ("negative_gap", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -291,25 +291,36 @@ class Solver:
     def solve_logged(self, tau: float, max_iters: int, cert_every: int, path: str, relative: bool = True):
         """bdrs_solve one certificate block at a time, appending one JSON line per
         certificate to `path` (k, eps, L, U, gap, rel_gap, the best bounds, delta,
-        cost_Z, n_nonfinite and the wall-clock seconds since the call).  The
-        iterates and certificates are those of solve(tau, max_iters, cert_every)
-        from the same state; returns the same (reached, certificate)."""
+        cost_Z, n_nonfinite, negative_gap and the wall-clock seconds since the
+        call).  The first block ends at the next multiple of cert_every, the
+        others run cert_every iterations and the last one the remainder, so the
+        iterates and certificates are those of solve(tau, max_iters,
+        cert_every) from the same state; returns the same (reached,
+        certificate)."""
         import json
         import time
         t0 = time.perf_counter()
+        k0 = self.iterations()
         done, ok, ce = 0, False, None
         keys = ("k", "eps", "L", "U", "gap", "rel_gap", "L_best", "U_best", "rel_gap_best", "k_L_best",
-                "k_U_best", "delta", "cost_Z", "n_nonfinite")
+                "k_U_best", "delta", "cost_Z", "n_nonfinite", "negative_gap")
         with open(path, "a") as log:
             while done < max_iters and not ok:
-                block = min(cert_every, max_iters - done)
+                to_grid = cert_every - (k0 + done) % cert_every
+                block = min(to_grid, max_iters - done)
                 ok, ce = self.solve(tau, block, cert_every, relative)
-                done += block
+                done = int(ce["k"]) + 1 - k0
                 rec = {key: ce[key] for key in keys}
                 rec["t_wall"] = round(time.perf_counter() - t0, 6)
                 log.write(json.dumps(rec) + "\n")
                 log.flush()
         return ok, ce
+
+    def iterations(self) -> int:
+        """Finished iterations k of the solver (synchronises its stream)."""
+        k = ctypes.c_int64()
+        check(lib().bdrs_get_state(self._h, None, None, None, None, None, None, ctypes.byref(k)))
+        return k.value
 
     def restore_best(self) -> int:
         """Makes the retained lowest-gap state current (keep_best=True); returns its iteration count."""

@@ -149,7 +149,8 @@ bdrs_status check_params(const bdrs_params* p, size_t need) {
     return fail(BDRS_E_INVALID, "cost_scale must be finite and > 0");
   if (!(std::isfinite(p->eta) && p->eta > 0)) return fail(BDRS_E_INVALID, "eta must be finite and > 0");
   if (!(p->lambda >= 1.0 && p->lambda < 2.0)) return fail(BDRS_E_INVALID, "lambda must lie in [1, 2)");
-  if (!(std::isfinite(p->omega) && p->omega >= 0)) return fail(BDRS_E_INVALID, "omega must be finite and >= 0");
+  if (!(std::isfinite(p->omega) && p->omega > 0))
+    return fail(BDRS_E_INVALID, "omega must be finite and > 0 (a bound Omega >= osc(C), Prop. 3)");
   const uint32_t known = BDRS_F_REPAIR | BDRS_F_OLD_KERNEL | BDRS_F_NO_MOMENTUM | BDRS_F_DEBIASED | BDRS_F_NO_GRAPH |
                          BDRS_F_KEEP_BEST_STATE;
   if (p->flags & ~known) return fail(BDRS_E_INVALID, "unknown flags 0x%x", p->flags);
@@ -199,15 +200,8 @@ uint64_t spread2(uint64_t v) {
   return v;
 }
 
-struct HostSide {
-  std::vector<float> abs, off;
-  std::vector<TileRec> tile;
-  std::vector<int> perm, iperm;
-  std::vector<double> marg, logm;
-};
-
-void build_side(const std::vector<float>& pts, const std::vector<double>& w, int count, int dim,
-                const double origin[3], const SideShape& sh, HostSide& hs) {
+void build_side(const float* pts, const double* w, int count, int dim, const double origin[3], const SideShape& sh,
+                HostSide& hs) {
   // tile order: Morton order of the quantised coordinates
   double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   for (int d = 0; d < dim; ++d) {
@@ -437,6 +431,10 @@ hipError_t copy_best(bdrs_solver s, bool to_best) {
 }
 
 bdrs_status cert_from_record(bdrs_solver s, const double* h, bool repair, bdrs_cert* out) {
+  // Prop. 3 gives L <= p* <= U for every certificate, hence also
+  // U_best = min U >= p* >= max L = L_best; a computed gap below this
+  // tolerance (relative to U) contradicts it and invalidates the bounds.
+  constexpr double kNegGapTol = 1e-9;
   bdrs_cert ce;
   ce.k = (int64_t)h[0];
   ce.eps = h[1];
@@ -448,13 +446,17 @@ bdrs_status cert_from_record(bdrs_solver s, const double* h, bool repair, bdrs_c
   ce.gap = ce.U - ce.L;
   ce.rel_gap = ce.U > 1e-300 ? ce.gap / ce.U : ce.gap;
   ce.repaired_cost = repair ? h[8] : NAN;
-  if (ce.U < s->U_best) {
-    s->U_best = ce.U;
-    s->kU = ce.k;
-  }
-  if (ce.L > s->L_best) {
-    s->L_best = ce.L;
-    s->kL = ce.k;
+  const bool finite = ce.n_nonfinite == 0 && std::isfinite(ce.L) && std::isfinite(ce.U);
+  const bool neg_own = ce.gap < -kNegGapTol * std::fabs(ce.U);
+  if (finite && !neg_own) {  // an invalid certificate is not folded into the best bounds
+    if (ce.U < s->U_best) {
+      s->U_best = ce.U;
+      s->kU = ce.k;
+    }
+    if (ce.L > s->L_best) {
+      s->L_best = ce.L;
+      s->kL = ce.k;
+    }
   }
   ce.U_best = s->U_best;
   ce.L_best = s->L_best;
@@ -462,9 +464,16 @@ bdrs_status cert_from_record(bdrs_solver s, const double* h, bool repair, bdrs_c
   ce.k_L_best = s->kL;
   const double g = s->U_best - s->L_best;
   ce.rel_gap_best = s->U_best > 1e-300 ? g / s->U_best : g;
+  const bool neg_best = std::isfinite(g) && g < -kNegGapTol * std::fabs(s->U_best);
+  ce.negative_gap = (neg_own || neg_best) ? 1 : 0;
   if (out) *out = ce;
-  if (ce.n_nonfinite > 0 || !std::isfinite(ce.L) || !std::isfinite(ce.U))
+  if (!finite)
     return fail(BDRS_E_NUMERIC, "non-finite values in the certificate at iteration %lld", (long long)ce.k);
+  if (ce.negative_gap)
+    return fail(BDRS_E_NUMERIC,
+                "negative duality gap at iteration %lld: U - L = %.6e, U_best - L_best = %.6e "
+                "(Prop. 3 gives L <= p* <= U: float32 error in the sweeps or omega below osc(C))",
+                (long long)ce.k, ce.gap, g);
   if (s->L.keep_best && ce.rel_gap < s->best_rel) {
     // the state after iteration k (the certified one) becomes the retained state
     const hipError_t e = copy_best(s, true);
@@ -511,19 +520,19 @@ bdrs_status enqueue_repair(bdrs_solver s) {
   return BDRS_OK;
 }
 
-size_t row_sweep_items(const bdrs_solver s) { return (size_t)(s->L.R.np / kSweepBlock) * s->L.splits_row; }
-size_t col_sweep_items(const bdrs_solver s) { return (size_t)(s->L.C.np / kSweepBlock) * s->L.splits_col; }
+size_t row_sweep_items(const Layout& L) { return (size_t)(L.R.np / kSweepBlock) * L.splits_row; }
+size_t col_sweep_items(const Layout& L) { return (size_t)(L.C.np / kSweepBlock) * L.splits_col; }
 
-BatchLayout batch_layout(const std::vector<bdrs_solver>& sv) {
+BatchLayout batch_layout(const std::vector<const Layout*>& ls) {
   BatchLayout B{};
-  for (bdrs_solver s : sv) {
-    B.n_rs += row_sweep_items(s);
-    B.n_cs += col_sweep_items(s);
-    B.n_rf += s->L.R.ntiles;
-    B.n_cf += s->L.C.ntiles;
-    B.n_ce += s->L.cert_blocks;
+  for (const Layout* L : ls) {
+    B.n_rs += row_sweep_items(*L);
+    B.n_cs += col_sweep_items(*L);
+    B.n_rf += L->R.ntiles;
+    B.n_cf += L->C.ntiles;
+    B.n_ce += L->cert_blocks;
   }
-  const size_t count = sv.size();
+  const size_t count = ls.size();
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -542,7 +551,16 @@ BatchLayout batch_layout(const std::vector<bdrs_solver>& sv) {
   return B;
 }
 
-size_t BatchEngine::bytes_for(const std::vector<bdrs_solver>& members) { return batch_layout(members).total; }
+std::vector<const Layout*> layouts_of(const std::vector<bdrs_solver>& members) {
+  std::vector<const Layout*> ls;
+  for (bdrs_solver s : members) ls.push_back(&s->L);
+  return ls;
+}
+
+size_t BatchEngine::bytes_for(const std::vector<bdrs_solver>& members) { return batch_layout(layouts_of(members)).total; }
+size_t BatchEngine::bytes_for_layouts(const std::vector<const Layout*>& layouts) {
+  return batch_layout(layouts).total;
+}
 
 BatchEngine::~BatchEngine() {
   if (exec_) (void)hipGraphExecDestroy(exec_);  // teardown: nothing to report
@@ -558,7 +576,7 @@ hipError_t BatchEngine::bind(const std::vector<bdrs_solver>& members, char* ws, 
   ws_ = ws;
   st_ = st;
   iters_ = block_iters;
-  B_ = batch_layout(members_);
+  B_ = batch_layout(layouts_of(members_));
   dim_ = members_.empty() ? 0 : members_[0]->prm.dim;
   std::vector<LaunchCtx> descs;
   std::vector<BatchItem> rs, cs, rf, cf, ce;
@@ -592,17 +610,22 @@ hipError_t BatchEngine::bind(const std::vector<bdrs_solver>& members, char* ws, 
   up(B_.items_ce, ce.data(), ce.size() * sizeof(BatchItem));
   up(B_.probs, probs.data(), probs.size() * sizeof(int));
   if (r == hipSuccess) r = hipStreamSynchronize(st_);  // host vectors go out of scope
-  if (r == hipSuccess && use_graph && !members_.empty()) {
-    hipGraph_t g = nullptr;
-    r = hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal);
-    if (r == hipSuccess) {
-      const hipError_t r2 = enqueue(st_);
-      r = hipStreamEndCapture(st_, &g);
-      if (r == hipSuccess) r = r2;
-    }
-    if (r == hipSuccess) r = hipGraphInstantiate(&exec_, g, nullptr, nullptr, 0);
-    if (g) (void)hipGraphDestroy(g);
+  if (r == hipSuccess && use_graph) r = capture();
+  return r;
+}
+
+hipError_t BatchEngine::capture() {
+  if (exec_ || members_.empty()) return hipSuccess;
+  hipGraph_t g = nullptr;
+  hipError_t r = hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal);
+  if (r == hipSuccess) {
+    const hipError_t r2 = enqueue(st_);
+    r = hipStreamEndCapture(st_, &g);
+    if (r == hipSuccess) r = r2;
   }
+  if (r == hipSuccess) r = hipGraphInstantiate(&exec_, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (r != hipSuccess) exec_ = nullptr;
   return r;
 }
 
@@ -795,31 +818,47 @@ bdrs_status download_inputs(const bdrs_params* p, std::vector<float>& hx, std::v
   return BDRS_OK;
 }
 
-bdrs_status create_from_host(const bdrs_params* p, const float* px, const float* py, const double* pr,
-                             const double* pc, bdrs_solver* out, int reserve_row, int reserve_col) {
-  *out = nullptr;
+bdrs_status prepare_image(const bdrs_params* p, const float* px, const float* py, const double* pr, const double* pc,
+                          HostImage& img) {
   const int m = p->m, n = p->n, dim = p->dim;
-  hipStream_t stream = (hipStream_t)p->stream;
-  const std::vector<float> hx(px, px + (size_t)m * dim), hy(py, py + (size_t)n * dim);
-  const std::vector<double> hr(pr, pr + m), hc(pc, pc + n);
-
   // contents: finite coordinates, strictly positive marginals of unit mass (Eq. 1)
-  for (size_t i = 0; i < hx.size(); ++i)
-    if (!std::isfinite(hx[i])) return fail(BDRS_E_INVALID, "x has a non-finite entry at %zu", i);
-  for (size_t i = 0; i < hy.size(); ++i)
-    if (!std::isfinite(hy[i])) return fail(BDRS_E_INVALID, "y has a non-finite entry at %zu", i);
+  for (size_t i = 0; i < (size_t)m * dim; ++i)
+    if (!std::isfinite(px[i])) return fail(BDRS_E_INVALID, "x has a non-finite entry at %zu", i);
+  for (size_t i = 0; i < (size_t)n * dim; ++i)
+    if (!std::isfinite(py[i])) return fail(BDRS_E_INVALID, "y has a non-finite entry at %zu", i);
   double sr = 0, sc = 0;
   for (int i = 0; i < m; ++i) {
-    if (!(hr[i] > 0 && std::isfinite(hr[i]))) return fail(BDRS_E_INVALID, "r[%d] is not finite and > 0", i);
-    sr += hr[i];
+    if (!(pr[i] > 0 && std::isfinite(pr[i]))) return fail(BDRS_E_INVALID, "r[%d] is not finite and > 0", i);
+    sr += pr[i];
   }
   for (int j = 0; j < n; ++j) {
-    if (!(hc[j] > 0 && std::isfinite(hc[j]))) return fail(BDRS_E_INVALID, "c[%d] is not finite and > 0", j);
-    sc += hc[j];
+    if (!(pc[j] > 0 && std::isfinite(pc[j]))) return fail(BDRS_E_INVALID, "c[%d] is not finite and > 0", j);
+    sc += pc[j];
   }
   if (std::fabs(sr - 1.0) > 1e-9) return fail(BDRS_E_INVALID, "r must sum to 1 (sum - 1 = %.3e)", sr - 1.0);
   if (std::fabs(sc - 1.0) > 1e-9) return fail(BDRS_E_INVALID, "c must sum to 1 (sum - 1 = %.3e)", sc - 1.0);
+  img.m = m;
+  img.n = n;
+  img.dim = dim;
+  // common origin: centre of the joint bounding box (keeps coordinates small)
+  for (int d = 0; d < 3; ++d) img.origin[d] = 0.0;
+  for (int d = 0; d < dim; ++d) {
+    double lo = px[d], hi = px[d];
+    for (int i = 0; i < m; ++i) lo = std::min(lo, (double)px[(size_t)i * dim + d]), hi = std::max(hi, (double)px[(size_t)i * dim + d]);
+    for (int j = 0; j < n; ++j) lo = std::min(lo, (double)py[(size_t)j * dim + d]), hi = std::max(hi, (double)py[(size_t)j * dim + d]);
+    img.origin[d] = (double)(float)(0.5 * (lo + hi));
+  }
+  build_side(px, pr, m, dim, img.origin, side_shape(m), img.R);
+  build_side(py, pc, n, dim, img.origin, side_shape(n), img.C);
+  return BDRS_OK;
+}
 
+bdrs_status create_from_image(const bdrs_params* p, const HostImage& img, bdrs_solver* out, int reserve_row,
+                              int reserve_col) {
+  *out = nullptr;
+  const int m = p->m, n = p->n, dim = p->dim;
+  if (img.m != m || img.n != n || img.dim != dim) return fail(BDRS_E_INVALID, "host image does not match the sizes");
+  hipStream_t stream = (hipStream_t)p->stream;
   const Layout L = make_layout(m, n, dim, reserve_row, reserve_col, (p->flags & BDRS_F_KEEP_BEST_STATE) != 0);
   if (p->workspace_bytes < L.total)  // e.g. the tuning table changed since the workspace was sized
     return fail(BDRS_E_NOMEM, "workspace too small: %zu bytes given, %zu needed", p->workspace_bytes, L.total);
@@ -827,19 +866,9 @@ bdrs_status create_from_host(const bdrs_params* p, const float* px, const float*
   s->prm = *p;
   s->L = L;
   fill_ctx(s);
-
-  // common origin: centre of the joint bounding box (keeps coordinates small)
-  double origin[3] = {0, 0, 0};
-  for (int d = 0; d < dim; ++d) {
-    double lo = hx[d], hi = hx[d];
-    for (int i = 0; i < m; ++i) lo = std::min(lo, (double)hx[(size_t)i * dim + d]), hi = std::max(hi, (double)hx[(size_t)i * dim + d]);
-    for (int j = 0; j < n; ++j) lo = std::min(lo, (double)hy[(size_t)j * dim + d]), hi = std::max(hi, (double)hy[(size_t)j * dim + d]);
-    origin[d] = (double)(float)(0.5 * (lo + hi));
-  }
-  for (int d = 0; d < 3; ++d) s->ctx.origin[d] = d < dim ? origin[d] : 0.0;
-  HostSide R, C;
-  build_side(hx, hr, m, dim, origin, s->L.R, R);
-  build_side(hy, hc, n, dim, origin, s->L.C, C);
+  for (int d = 0; d < 3; ++d) s->ctx.origin[d] = img.origin[d];
+  const HostSide& R = img.R;
+  const HostSide& C = img.C;
 
   const LaunchCtx& c = s->ctx;
   auto up = [&](void* dst, const void* src, size_t bytes) {
@@ -883,13 +912,22 @@ bdrs_status create_from_host(const bdrs_params* p, const float* px, const float*
   chk(hipMemsetAsync(c.st.lt[1], 0, sizeof(double) * c.cols.np, stream));
   chk(hipMemsetAsync(c.cert_out, 0, sizeof(double) * kCertSlots, stream));
   if (e == hipSuccess) e = launch_prologue(c);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);  // the host image may go out of scope
   if (e != hipSuccess) {
     delete s;
     return fail(BDRS_E_DEVICE, "HIP error %s while initialising the workspace", hipGetErrorString(e));
   }
   *out = s;
   return BDRS_OK;
+}
+
+bdrs_status create_from_host(const bdrs_params* p, const float* px, const float* py, const double* pr,
+                             const double* pc, bdrs_solver* out, int reserve_row, int reserve_col) {
+  *out = nullptr;
+  HostImage img;
+  const bdrs_status st = prepare_image(p, px, py, pr, pc, img);
+  if (st != BDRS_OK) return st;
+  return create_from_image(p, img, out, reserve_row, reserve_col);
 }
 
 }  // namespace bdrs_host

@@ -51,7 +51,30 @@ bdrs_status check_sizes(const bdrs_params* p);
 bdrs_status check_params(const bdrs_params* p, size_t need = 0);
 bdrs_status check_device();
 
-// Builds a solver from host copies of the inputs (contents validated here).
+// One point set in tile order on the host: what bdrs_create uploads for it.
+struct HostSide {
+  std::vector<float> abs, off;
+  std::vector<TileRec> tile;
+  std::vector<int> perm, iperm;
+  std::vector<double> marg, logm;
+};
+
+// A problem prepared on the host (contents validated, points in Morton tile
+// order, tile records and offsets built); independent of the split counts.
+struct HostImage {
+  int m = 0, n = 0, dim = 0;
+  double origin[3] = {0, 0, 0};
+  HostSide R, C;
+};
+
+// Validates the contents of host copies of the inputs and builds the image.
+bdrs_status prepare_image(const bdrs_params* p, const float* hx, const float* hy, const double* hr,
+                          const double* hc, HostImage& img);
+// Lays out the workspace, uploads the image, initialises the state of
+// Algorithm 1 (synchronises p->stream).
+bdrs_status create_from_image(const bdrs_params* p, const HostImage& img, bdrs_solver* out, int reserve_row = 0,
+                              int reserve_col = 0);
+// Both steps: a solver from host copies of the inputs.
 bdrs_status create_from_host(const bdrs_params* p, const float* hx, const float* hy, const double* hr,
                              const double* hc, bdrs_solver* out, int reserve_row = 0, int reserve_col = 0);
 // Device -> host copies of a problem's inputs (synchronises p->stream).
@@ -71,10 +94,15 @@ struct BatchLayout {
 class BatchEngine {
  public:
   static size_t bytes_for(const std::vector<bdrs_solver>& members);
+  // the same from the members' workspace layouts (before they are created)
+  static size_t bytes_for_layouts(const std::vector<const Layout*>& layouts);
   // (re)binds the members: uploads descriptors and work lists into `ws`
   // (at least bytes_for(members) bytes) and, with a graph, captures one block
   hipError_t bind(const std::vector<bdrs_solver>& members, char* ws, int block_iters, bool use_graph,
                   hipStream_t st);
+  // captures one block of the bound members as a graph (no-op if captured)
+  hipError_t capture();
+  bool captured() const { return exec_ != nullptr; }
   hipError_t run_block();                               // enqueue one block (+ certificates)
   hipError_t read_records(std::vector<double>& rec);    // D2H of the members' records, synchronises
   const std::vector<bdrs_solver>& members() const { return members_; }

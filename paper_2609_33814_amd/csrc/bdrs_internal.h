@@ -87,7 +87,8 @@ struct StateDev {
 };
 
 // Partial reduction of one (split, output): shift M (log2, float64), shifted
-// sum S and shifted cost-weighted sum N (certificate sweeps).  16 bytes.
+// sum S and shifted cost-weighted sum N (certificate sweeps), and the input
+// slot J that set M.  24 bytes.
 struct PartialRec {
   double M;
   float S, N;

@@ -775,7 +775,8 @@ __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, 
     return;
   }
   if (kind == kFinishRow) {
-    // Algorithm 1: log alpha-hat^k = log r - LSE, log alpha^k = (1-lambda) log alpha^{k-1} + lambda log alpha-hat^k
+    // row update of Algorithm 1: the unrelaxed row scaling normalises the rows to r; the
+    // relaxed one mixes it with the previous relaxed scaling, weight lambda on the new one
     const double eps = eps_of(ctrl, eps_arg, kofs);
     const double kap2 = kLog2eD * ctrl->scale / eps;
     double colw = 0.0;
@@ -807,7 +808,8 @@ __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, 
     const double lb1 = pre_s;
     const double lb = fma(lam, lbh, (1.0 - lam) * lb1);  // log beta^k (rounding as for alpha)
     if (cert) {
-      // Algorithm 2: mu_j = N_j / D_j, d_j = M_j + log D_j, log s_j = log t_j + d_j
+      // certificate statistics of the intermediate plan's column (Prop. 3, Algorithm 2):
+      // its mean cost (cost-weighted over plain merged sums) and the log of its mass
       c.st.mu[p] = ctrl->scale * mg.N / mg.S;
       c.st.logs[p] = (cur ? pre_t1 : pre_t0) + mg.lse;
     }

@@ -91,6 +91,49 @@ inline int pick_admission(const std::vector<double>& queued_work, const std::vec
   return -1;
 }
 
+// Places a request's workspace together with the region of the batch engine
+// (descriptors and work lists of all running requests), which grows with
+// every admission: *eng_off / *eng_bytes describe the engine's current region
+// (*eng_bytes = 0: none) and eng_need what it needs once the request runs.
+// If the region is large enough and the workspace fits beside it, only the
+// workspace is placed.  Otherwise the region is released and the workspace
+// and a region of eng_need bytes are taken; if either does not fit, both are
+// given back and the old region is taken again (it fits: the free ranges are
+// the same as before it was released), and the request waits.  *moved
+// reports whether the engine's region changed (its contents must then be
+// bound again).  Returns true when the request is placed (workspace at
+// *ws_off).  With nothing running, a waiting request therefore fails only if
+// its workspace and its engine region together exceed the pool.
+inline bool place_with_engine(PoolAlloc& pool, size_t ws_bytes, size_t eng_need, size_t* ws_off, size_t* eng_off,
+                              size_t* eng_bytes, bool* moved) {
+  *moved = false;
+  if (pool_align(eng_need) <= *eng_bytes && pool.alloc(ws_bytes, ws_off)) return true;
+  const size_t old_off = *eng_off, old_bytes = *eng_bytes;
+  if (old_bytes) pool.release(old_off);
+  size_t wo = 0, eo = 0;
+  if (pool.alloc(ws_bytes, &wo)) {
+    if (pool.alloc(eng_need, &eo)) {
+      *ws_off = wo;
+      *eng_off = eo;
+      *eng_bytes = pool_align(eng_need);
+      *moved = true;
+      return true;
+    }
+    pool.release(wo);
+  }
+  if (old_bytes) {
+    size_t back = 0;
+    if (pool.alloc(old_bytes, &back)) {
+      *moved = back != old_off;
+      *eng_off = back;
+    } else {  // cannot happen (see above); the region is then gone
+      *eng_bytes = 0;
+      *moved = true;
+    }
+  }
+  return false;
+}
+
 }  // namespace bdrs_sched
 
 #endif  // BDRS_SCHED_H_

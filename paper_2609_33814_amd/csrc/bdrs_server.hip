@@ -1,14 +1,19 @@
 // Solve server: continuous batching of independent OT solves (bdrs_server_*).
 //
-// A worker thread owns the GPU work.  Requests wait in a FIFO queue; at every
-// block boundary the worker admits requests from the head of the queue while
-// a slot is free and the pool can hold the request's workspace (with the
+// bdrs_server_submit validates a request and prepares its host image (points
+// in Morton tile order, tile records) on the caller's thread, so the worker
+// only uploads it.  A worker thread owns the GPU work.  Requests wait in a
+// FIFO queue; at every block boundary the worker admits requests from the
+// head of the queue while a slot is free and the pool can hold the request's
+// workspace together with the batch engine's grown work lists (with the
 // size-aware policy, requests above a work threshold run one at a time, in
 // arrival order, and smaller ones may pass a waiting large one), runs one
 // block of iterations of all running requests through the batch engine,
 // reads every request's certificate, and retires the finished ones (their
-// pool memory is reused by the next admissions).  The per-request arithmetic
-// is the single-problem one, so results do not depend on the mix.
+// pool memory is reused by the next admissions).  A block whose set of
+// running requests is the same as in the previous block is captured once as a
+// graph and replayed until the set changes.  The per-request arithmetic is
+// the single-problem one, so results do not depend on the mix.
 #include "bdrs_host.h"
 #include "bdrs_sched.h"
 
@@ -32,8 +37,7 @@ using bdrs_sched::PoolAlloc;
 struct Request {
   uint64_t ticket = 0;
   bdrs_params prm{};
-  std::vector<float> x, y;
-  std::vector<double> r, c;
+  HostImage img;          // prepared at submit; released when the request is done
   double tau = 0;
   int tau_relative = 1;
   int max_iters = 0;
@@ -83,14 +87,26 @@ void finish(bdrs_server_* sv, const std::shared_ptr<Request>& rq, int status) {
     sv->alloc->release(rq->off);
     rq->bytes = 0;
   }
-  rq->x.clear();
-  rq->y.clear();
-  rq->r.clear();
-  rq->c.clear();
-  rq->x.shrink_to_fit();
-  rq->y.shrink_to_fit();
-  rq->r.shrink_to_fit();
-  rq->c.shrink_to_fit();
+  rq->img = HostImage();
+}
+
+// Puts a running request back at the head of the queue (its solver and
+// workspace are given up; it restarts from iteration 0 when admitted again).
+// Called with the lock held.
+void requeue(bdrs_server_* sv, const std::shared_ptr<Request>& rq) {
+  if (rq->solver) {
+    bdrs_destroy(rq->solver);
+    rq->solver = nullptr;
+  }
+  if (rq->bytes) {
+    sv->alloc->release(rq->off);
+    rq->bytes = 0;
+  }
+  rq->iters = 0;
+  rq->res.state = 0;
+  rq->res.cert = bdrs_cert{};
+  rq->res.cert.repaired_cost = NAN;
+  sv->queue.push_front(rq);
 }
 
 }  // namespace
@@ -99,7 +115,8 @@ void bdrs_server_::run() {
   const bool dev_ok = hipSetDevice(device) == hipSuccess;  // else every request fails with E_DEVICE
   BatchEngine eng;
   size_t eng_off = 0, eng_bytes = 0;
-  bool eng_valid = false;
+  bool eng_valid = false;  // the engine is bound to the current running set at eng_off
+  bool stable = false;     // the running set is the same as in the previous block
   std::vector<double> rec;
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
@@ -121,29 +138,50 @@ void bdrs_server_::run() {
         cv_done.notify_all();
         continue;
       }
+      // the request's workspace and the engine's work lists for the grown
+      // running set are placed together, so an admitted request always runs
+      const Layout lay = make_layout(rq->prm.m, rq->prm.n, rq->prm.dim);
+      std::vector<const Layout*> lays;
+      for (auto& r : running) lays.push_back(&r->solver->L);
+      lays.push_back(&lay);
+      const size_t need = BatchEngine::bytes_for_layouts(lays);
       size_t off = 0;
-      if (!alloc->alloc(rq->bytes, &off)) break;  // the candidate waits for memory; nothing passes it
+      bool moved = false;
+      const bool placed = bdrs_sched::place_with_engine(*alloc, lay.total, need, &off, &eng_off, &eng_bytes, &moved);
+      if (moved) eng_valid = false;
+      if (!placed) {
+        if (running.empty()) {
+          // it can never fit (e.g. the tuning table grew its layout since it was submitted)
+          queue.erase(pick);
+          finish(this, rq, BDRS_E_NOMEM);
+          cv_done.notify_all();
+          continue;
+        }
+        break;  // the candidate waits for memory; nothing passes it
+      }
       queue.erase(pick);
       rq->off = off;
+      rq->bytes = lay.total;
       rq->prm.workspace = pool + off;
-      rq->prm.workspace_bytes = rq->bytes;
+      rq->prm.workspace_bytes = lay.total;
       rq->prm.stream = stream;
       lk.unlock();
       bdrs_solver s = nullptr;
-      const bdrs_status st = create_from_host(&rq->prm, rq->x.data(), rq->y.data(), rq->r.data(), rq->c.data(), &s);
+      const bdrs_status st = create_from_image(&rq->prm, rq->img, &s);  // upload only
       lk.lock();
       if (st != BDRS_OK) {
         finish(this, rq, st);
         cv_done.notify_all();
         continue;
       }
-      rq->solver = s;
+      rq->solver = s;  // the host image stays until the request is done (a requeue re-uploads it)
       rq->res.state = 1;
       rq->res.t_admit = now();
       running.push_back(rq);
       changed = true;
     }
     if (running.empty()) {
+      stable = false;
       if (stop) break;
       cv_work.wait(lk, [&] { return stop || !queue.empty(); });
       continue;
@@ -152,21 +190,17 @@ void bdrs_server_::run() {
       std::vector<bdrs_solver> mem;
       for (auto& rq : running) mem.push_back(rq->solver);
       const size_t need = BatchEngine::bytes_for(mem);
-      if (need > eng_bytes) {
-        if (eng_bytes) alloc->release(eng_off);
-        eng_bytes = 0;
-        if (!alloc->alloc(need, &eng_off)) {
-          // no room for the work lists: retire the newest request with NOMEM
-          auto rq = running.back();
-          running.pop_back();
-          finish(this, rq, BDRS_E_NOMEM);
-          cv_done.notify_all();
-          eng_valid = false;
-          continue;
-        }
-        eng_bytes = align_up(need);
+      if (align_up(need) > eng_bytes) {
+        // not reached: admission reserved the engine's room for this set.  If
+        // it is, the newest request goes back to the head of the queue.
+        auto rq = running.back();
+        running.pop_back();
+        requeue(this, rq);
+        eng_valid = false;
+        continue;
       }
       lk.unlock();
+      // eager blocks until the set has stayed the same for one block
       const hipError_t e = eng.bind(mem, pool + eng_off, block_iters, false, stream);
       lk.lock();
       if (e != hipSuccess) {
@@ -177,9 +211,12 @@ void bdrs_server_::run() {
         continue;
       }
       eng_valid = true;
+      stable = false;
     }
     lk.unlock();
-    hipError_t e = eng.run_block();
+    hipError_t e = hipSuccess;
+    if (stable && !eng.captured()) e = eng.capture();  // replayed until the set changes
+    if (e == hipSuccess) e = eng.run_block();
     if (e == hipSuccess) e = eng.read_records(rec);
     lk.lock();
     if (e != hipSuccess) {
@@ -202,7 +239,8 @@ void bdrs_server_::run() {
       else if (rq->iters >= rq->max_iters) finish(this, rq, BDRS_NOT_CONVERGED);
       else still.push_back(rq);
     }
-    if (still.size() != running.size()) {
+    stable = still.size() == running.size();
+    if (!stable) {
       running.swap(still);
       eng_valid = false;
       cv_done.notify_all();
@@ -251,6 +289,7 @@ bdrs_status bdrs_server_create(void* pool, size_t pool_bytes, int32_t max_slots,
 bdrs_status bdrs_server_submit(bdrs_server sv, const bdrs_request* rq, uint64_t* ticket) {
   if (!sv) return fail(BDRS_E_INVALID, "server is NULL");
   if (!rq || !ticket) return fail(BDRS_E_INVALID, "request and ticket are required");
+  const double t_call = sv->now();  // the host preparation below counts into the latency
   bdrs_params p{};
   p.m = rq->m;
   p.n = rq->n;
@@ -272,14 +311,15 @@ bdrs_status bdrs_server_submit(bdrs_server sv, const bdrs_request* rq, uint64_t*
     return fail(BDRS_E_INVALID, "max_iters must be a positive multiple of block_iters (%d)", sv->block_iters);
   auto r = std::make_shared<Request>();
   r->prm = p;
-  r->bytes = make_layout(p.m, p.n, p.dim).total;
+  const Layout lay = make_layout(p.m, p.n, p.dim);
   r->work = (double)p.m * (double)p.n;
-  if (align_up(r->bytes) > sv->alloc->size())
-    return fail(BDRS_E_NOMEM, "request needs %zu bytes, the pool holds %zu", r->bytes, sv->alloc->size());
-  r->x.assign(rq->x, rq->x + (size_t)p.m * p.dim);
-  r->y.assign(rq->y, rq->y + (size_t)p.n * p.dim);
-  r->r.assign(rq->r, rq->r + p.m);
-  r->c.assign(rq->c, rq->c + p.n);
+  // its workspace and the batch engine's work lists for it alone must fit the pool
+  const size_t alone = align_up(lay.total) + align_up(BatchEngine::bytes_for_layouts({&lay}));
+  if (alone > sv->alloc->size())
+    return fail(BDRS_E_NOMEM, "request needs %zu bytes with its work lists, the pool holds %zu", alone,
+                sv->alloc->size());
+  // contents validated and the host image built here, on the caller's thread
+  if ((st = prepare_image(&p, rq->x, rq->y, rq->r, rq->c, r->img)) != BDRS_OK) return st;
   r->tau = rq->tau;
   r->tau_relative = rq->tau_relative;
   r->max_iters = rq->max_iters;
@@ -287,7 +327,7 @@ bdrs_status bdrs_server_submit(bdrs_server sv, const bdrs_request* rq, uint64_t*
   if (sv->stop) return fail(BDRS_E_STATE, "server is stopping");
   r->ticket = sv->next_ticket++;
   r->res.state = 0;
-  r->res.t_submit = sv->now();
+  r->res.t_submit = t_call;
   r->res.cert.repaired_cost = NAN;
   sv->all[r->ticket] = r;
   sv->queue.push_back(r);

@@ -201,10 +201,102 @@ static void server_loop() {
     if (r.id == 1) CHECK(r.admitted_at >= 6);  // the second large one waited for the first
 }
 
+// Admission with the batch engine's region (place_with_engine): the engine
+// needs a region that grows with the running set; a request is admitted only
+// when its workspace and the grown region both fit, so no admitted request
+// ever finds the engine without room.  Random workloads in a tight pool, the
+// invariants checked after every admission and every retirement.
+static void engine_admission() {
+  using bdrs_sched::place_with_engine;
+  const size_t KB = 1024;
+  // exact cases: a pool of 10 units of 256 KiB
+  {
+    PoolAlloc pool(10 * 256 * KB);
+    size_t eoff = 0, ebytes = 0, w1 = 0, w2 = 0, w3 = 0;
+    bool moved = false;
+    CHECK(place_with_engine(pool, 3 * 256 * KB, 1 * 256 * KB, &w1, &eoff, &ebytes, &moved));
+    CHECK(moved && ebytes == 256 * KB && pool.used() == 4 * 256 * KB);
+    CHECK(place_with_engine(pool, 3 * 256 * KB, 2 * 256 * KB, &w2, &eoff, &ebytes, &moved));
+    CHECK(moved && ebytes == 2 * 256 * KB && pool.used() == 8 * 256 * KB);
+    // the workspace would fit (2 units free) but not with the grown region
+    // (2 + 3 units against the 2 free and the engine's 2): the request waits
+    // and the pool is as before (the engine's region taken again)
+    const size_t used = pool.used();
+    CHECK(!place_with_engine(pool, 2 * 256 * KB, 3 * 256 * KB, &w3, &eoff, &ebytes, &moved));
+    CHECK(pool.used() == used && ebytes == 2 * 256 * KB);
+    CHECK(pool.allocated().count(eoff) == 1);
+    // a region that is already large enough is left alone
+    pool.release(w1);
+    CHECK(place_with_engine(pool, 256 * KB, 2 * 256 * KB, &w3, &eoff, &ebytes, &moved));
+    CHECK(!moved && ebytes == 2 * 256 * KB);
+    check_pool(pool);
+  }
+  std::mt19937_64 rng(4242);
+  for (int trial = 0; trial < 200; ++trial) {
+    PoolAlloc pool((size_t)(8 + rng() % 24) * 256 * KB);
+    struct R {
+      size_t ws, items, off;
+      int blocks;
+    };
+    std::deque<R> queue;
+    for (int i = 0; i < 30; ++i)
+      queue.push_back(R{(size_t)(1 + rng() % 4) * 256 * KB - (rng() % 200), (size_t)(1 + rng() % 64) * KB, 0,
+                        1 + (int)(rng() % 5)});
+    std::vector<R> running;
+    size_t eoff = 0, ebytes = 0;
+    auto need_of = [&](const std::vector<R>& set, const R* extra) {
+      size_t n = 4 * KB;  // descriptors and the fixed part
+      for (auto& r : set) n += r.items;
+      if (extra) n += extra->items;
+      return n;
+    };
+    int guard = 0;
+    while ((!queue.empty() || !running.empty()) && ++guard < 10000) {
+      while (!queue.empty() && running.size() < 6) {
+        R r = queue.front();
+        bool moved = false;
+        const size_t before = pool.used();
+        const size_t need = need_of(running, &r);
+        if (!place_with_engine(pool, r.ws, need, &r.off, &eoff, &ebytes, &moved)) {
+          CHECK(pool.used() == before);
+          break;
+        }
+        queue.pop_front();
+        running.push_back(r);
+        // the engine's region holds the grown set's work lists
+        CHECK(ebytes >= pool_align(need_of(running, nullptr)));
+        CHECK(pool.allocated().count(eoff) == 1 && pool.allocated().at(eoff) == ebytes);
+      }
+      size_t sum = ebytes;
+      for (auto& r : running) sum += pool_align(r.ws);
+      CHECK(sum == pool.used());
+      // with nothing running a request waits only if it can never fit
+      if (running.empty() && !queue.empty()) {
+        const R& r = queue.front();
+        CHECK(pool.used() == ebytes);
+        CHECK(pool_align(r.ws) + pool_align(need_of({}, &r)) > pool.size());
+        queue.pop_front();  // the server rejects such a request at submit
+        continue;
+      }
+      std::vector<R> still;
+      for (auto& r : running) {
+        if (--r.blocks == 0) pool.release(r.off);
+        else still.push_back(r);
+      }
+      running.swap(still);
+      check_pool(pool);
+    }
+    CHECK(guard < 10000);
+    if (ebytes) pool.release(eoff);
+    CHECK(pool.used() == 0);
+  }
+}
+
 int main() {
   allocator_random();
   admission_cases();
   server_loop();
+  engine_admission();
   if (failures) return 1;
   std::printf("ok\n");
   return 0;

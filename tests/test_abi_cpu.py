@@ -62,7 +62,8 @@ def _good(**kw):
     ("cost_scale", float("nan"), bdrs.E_INVALID, "cost_scale"),
     ("eta", -1.0, bdrs.E_INVALID, "eta"), ("eta", float("inf"), bdrs.E_INVALID, "eta"),
     ("lam", 0.99, bdrs.E_INVALID, "lambda"), ("lam", 2.0, bdrs.E_INVALID, "lambda"),
-    ("omega", -1.0, bdrs.E_INVALID, "omega"),
+    ("omega", -1.0, bdrs.E_INVALID, "omega"), ("omega", 0.0, bdrs.E_INVALID, "omega"),
+    ("omega", float("inf"), bdrs.E_INVALID, "omega"),
     ("workspace", 0, bdrs.E_INVALID, "workspace"),
     ("workspace", 0x10010, bdrs.E_INVALID, "aligned"),
     ("workspace_bytes", 100, bdrs.E_NOMEM, "workspace"),

@@ -66,3 +66,58 @@ def test_batch_rejects_misaligned_and_mixed_dims():
     with pytest.raises(bdrs.BdrsError) as ei:
         bdrs.batch_solve([a, c], 0.01, 100, 50)
     assert ei.value.status == bdrs.E_STATE
+
+
+def test_batched_results_match_the_oracle():
+    """Every problem of a mixed batch (grids 8x8 to 24x24, eta = 0.5, captured
+    50-iteration blocks, stop at a 5% certified relative gap) against the
+    FP64 oracle's own run of Algorithm 1 with the certificate of Prop. 3
+    every 50 iterations: the same stopping iteration, and the relative gap,
+    U and L at that certificate within the trajectory bars."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_33814_amd import bdrs
+    import oracle_runs
+    sides = [16, 12, 24, 20, 16, 8]
+    probs = [inputs.grid_problem(s, 700 + 2 * i, 701 + 2 * i) for i, s in enumerate(sides)]
+    eta, tau, cap, every = 0.5, 0.05, 2000, 50
+    refs = oracle_runs.run_many([(p, eta, 1.0, cap, every, tau) for p in probs])
+    batch = [make(p, eta=eta) for p in probs]
+    st, certs, sts = bdrs.batch_solve(batch, tau, cap, every, use_graph=True)
+    assert st == bdrs.OK and all(x == bdrs.OK for x in sts)
+    assert len({c["k"] for c in certs}) > 1          # problems retired at different certificates
+    for i, (ce, ref) in enumerate(zip(certs, refs)):
+        print(f"batch member {i} (side {sides[i]}):", oracle_runs.compare_final(ce, ref, tau))
+        assert ce["negative_gap"] == 0
+
+
+def test_batched_256_member_certificate_matches_the_oracle():
+    """A batch with a 256x256 member (65536 points per side, 4.3e9 implicit
+    entries per sweep) next to 32x32 and 64x64 ones, eta = 0.1, 300
+    iterations in captured 50-iteration blocks: each member's fused
+    certificate at k = 299 against Prop. 3 / Algorithm 2 evaluated by the
+    oracle over all entries from the member's own state (the bars of a
+    certificate from an identical state)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_33814_amd import bdrs
+    from oracle import alg1, certificate
+    probs = [inputs.grid_problem(s, 4100 + 2 * i, 4101 + 2 * i) for i, s in enumerate([256, 32, 64])]
+    eta, iters, every = 0.1, 300, 50
+    batch = [make(p, eta=eta) for p in probs]
+    st, certs, sts = bdrs.batch_solve(batch, 0.0, iters, every, use_graph=True)
+    eps = alg1.schedule(eta, 1.0, iters - 1)
+    for p, sv, ce in zip(probs, batch, certs):
+        gs = sv.get_state()
+        assert ce["k"] == iters - 1 and gs["k"] == iters
+        npy = lambda key: gs[key].cpu().numpy()
+        ref = certificate.certificate(p.x, p.y, p.cost_scale, p.r, p.c, npy("lah"), npy("lbh"), npy("lt"), eps,
+                                      workers=16)
+        dU = abs(ce["U"] - ref["U"]) / ref["U"]
+        print(f"batched {p.m} points: dL {abs(ce['L'] - ref['L']) / abs(ref['L']):.1e} dU {dU:.1e} "
+              f"ddelta {abs(ce['delta'] - ref['delta']):.1e} gap {ce['rel_gap']:.6f} vs {ref['rel']:.6f}")
+        assert abs(ce["L"] - ref["L"]) <= 1e-9 * abs(ref["L"])
+        assert dU <= 1e-6
+        assert abs(ce["delta"] - ref["delta"]) <= 1e-4 * ref["delta"] + 2e-6
+        assert abs(ce["rel_gap"] - ref["rel"]) <= 1e-3 * abs(ref["rel"])
+        assert ce["n_nonfinite"] == 0 and ce["negative_gap"] == 0

@@ -117,3 +117,36 @@ def test_solve_logged_records_every_certificate(tmp_path):
         assert torch.equal(sa[key], sb[key]), key
     a.close()
     b.close()
+
+
+def test_solve_logged_from_a_misaligned_start(tmp_path):
+    """After step(7) the first logged block runs to the next multiple of
+    cert_every (k = 49), so the logged run certifies exactly where one
+    solve call from k = 7 does and stops at the same iteration, bit for bit;
+    a cap that is not a multiple of cert_every ends with the remainder."""
+    import json
+    from paper_2609_33814_amd import bdrs, inputs
+    prob = inputs.grid_problem(32, 11, 12)
+    d = torch.device("cuda:0")
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=d)
+    mk = lambda: bdrs.Solver(t(prob.x, torch.float32), t(prob.y, torch.float32), t(prob.r, torch.float64),
+                             t(prob.c, torch.float64), prob.cost_scale, eta=0.1)
+    for tau, cap in ((0.01, 5000), (0.0, 180)):
+        a, b = mk(), mk()
+        a.step(7)
+        b.step(7)
+        path = str(tmp_path / f"certs_{cap}.jsonl")
+        ok_a, ce_a = a.solve_logged(tau, cap, 50, path)
+        ok_b, ce_b = b.solve(tau, cap, 50)
+        assert ok_a == ok_b
+        recs = [json.loads(line) for line in open(path)]
+        ks = [r["k"] for r in recs]
+        assert ks[0] == 49 and all(k % 50 == 49 for k in ks[:-1]), ks
+        assert ks[-1] == ce_b["k"]
+        if not ok_b:
+            assert ce_b["k"] == 7 + cap - 1
+        for key in ("k", "L", "U", "rel_gap", "L_best", "U_best", "rel_gap_best", "delta"):
+            assert ce_a[key] == ce_b[key] == recs[-1][key], key
+        assert a.iterations() == b.iterations() == ce_b["k"] + 1
+        a.close()
+        b.close()

@@ -71,12 +71,16 @@ def test_server_rejects_and_isolates_bad_requests():
     assert ei.value.status == bdrs.E_INVALID
     bad = inputs.grid_problem(16, 5, 6)
     bad.r = bad.r.copy()
-    bad.r[3] = -1.0                                     # contents are checked at admission
-    tb = srv.submit(bad, max_iters=100)
+    bad.r[3] = -1.0                                     # contents are checked at submit
     tg = srv.submit(good, eta=0.3, tau=0.05, max_iters=2000)
-    rb, rg = srv.wait(tb), srv.wait(tg)
+    with pytest.raises(bdrs.BdrsError) as ei:
+        srv.submit(bad, max_iters=100)
+    assert ei.value.status == bdrs.E_INVALID and "r[3]" in str(ei.value)
+    with pytest.raises(bdrs.BdrsError) as ei:          # omega must be > 0
+        srv.submit(good, omega=0.0, max_iters=100)
+    assert ei.value.status == bdrs.E_INVALID
+    rg = srv.wait(tg)
     srv.close()
-    assert rb["status"] == bdrs.E_INVALID
     assert rg["status"] in (bdrs.OK, bdrs.NOT_CONVERGED) and rg["cert"]["k"] >= 49
 
 
@@ -102,6 +106,30 @@ def test_size_aware_policy_runs_large_requests_one_at_a_time():
     for prob, r, cap in ((big1, r1, 300), (big2, r2, 300), (small, r3, 100)):
         _, ce = alone(prob, eta, 0.0, cap, block)
         assert r["cert"]["U"] == ce["U"] and r["cert"]["L"] == ce["L"] and r["cert"]["k"] == ce["k"]
+
+
+def test_served_results_match_the_oracle():
+    """Requests of grids 8x8 to 24x24 (eta = 0.3, stop at a 2% certified
+    relative gap) served concurrently in a pool that holds a few at a time,
+    each against the FP64 oracle's own run of Algorithm 1 with the
+    certificate of Prop. 3 every block: the same stopping iteration, and the
+    relative gap, U and L at that certificate within the trajectory bars."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_33814_amd import bdrs
+    import oracle_runs
+    sides = [16, 24, 12, 20, 16, 24, 8, 20]
+    probs = [inputs.grid_problem(s, 800 + 2 * i, 801 + 2 * i) for i, s in enumerate(sides)]
+    eta, tau, cap, block = 0.3, 0.02, 3000, 50
+    refs = oracle_runs.run_many([(p, eta, 1.0, cap, block, tau) for p in probs])
+    need = max(bdrs.workspace_size(p.m, p.n, 2) for p in probs)
+    srv = bdrs.Server(pool_bytes=4 * need + (1 << 20), max_slots=4, block_iters=block)
+    tickets = [srv.submit(p, eta=eta, tau=tau, max_iters=cap) for p in probs]
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    for i, (r, ref) in enumerate(zip(res, refs)):
+        assert r["status"] == bdrs.OK, (i, r["status"])
+        print(f"served request {i} (side {sides[i]}):", oracle_runs.compare_final(r["cert"], ref, tau))
 
 
 def test_set_policy_validates():

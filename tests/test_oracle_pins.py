@@ -489,3 +489,29 @@ def test_rounding_of_obdrs_plans_scales_columns(lam):
         assert np.allclose(imp["y"], d["y"], rtol=1e-12, atol=0)
         assert cost >= pstar - 1e-12
     assert scaled > 0                             # the column step is exercised
+
+
+def test_column_statistics_in_threads_are_identical():
+    """The threaded evaluation (columns split into chunks) returns exactly the
+    single-threaded column statistics, on a ragged column count."""
+    prob = inputs.random_problem(300, 1300, 2, 21)
+    lah = np.random.default_rng(4).normal(0, 3, prob.m)
+    a = certificate.column_statistics(prob.x, prob.y, prob.cost_scale, 0.05, lah)
+    b = certificate.column_statistics(prob.x, prob.y, prob.cost_scale, 0.05, lah, workers=3)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+def test_trajectory_perturbation_hook():
+    """alg1.run's sensitivity hook: the identity map gives the plain FP64
+    trajectory bit for bit, and rounding every LSE result to float32 moves
+    the certificates by about float32's relative precision early on."""
+    prob = inputs.grid_problem(12, 3, 4)
+    _, plain, _ = alg1.run(prob, 0.3, 1.0, 100, cert_every=50)
+    _, ident, _ = alg1.run(prob, 0.3, 1.0, 100, cert_every=50, perturb=lambda v: v)
+    _, r32, _ = alg1.run(prob, 0.3, 1.0, 100, cert_every=50,
+                         perturb=lambda v: v.astype(np.float32).astype(np.float64))
+    for a, b, c in zip(plain, ident, r32):
+        assert a["U"] == b["U"] and a["L"] == b["L"]
+        assert a["U"] != c["U"]
+        assert abs(a["U"] - c["U"]) <= 1e-5 * a["U"]
