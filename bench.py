@@ -12,8 +12,10 @@ steps with the inputs resident in HBM.  Printed: one JSON line.
 Also reported: the dominant kernel's roofline fraction (sweep durations from
 HIP events recorded by the library on its own stream), the time to a 1%
 relative duality gap for plain BDRS (lambda = 1) and O-BDRS (lambda = 1.2,
-1.5, 1.99),
-and the FP64 oracle timed on the host on a bounded sample of the same sweeps.
+1.5, 1.99) from inputs resident (solver creation included), the 64-problem
+batch's makespan against sequential solves, the serve latencies (p50/p99)
+of Poisson requests against one-at-a-time FIFO, and the FP64 oracle timed
+on the host on a bounded sample of the same sweeps.
 """
 from __future__ import annotations
 
@@ -126,7 +128,7 @@ def cpu_baseline(prob, seconds: float = 12.0) -> dict:
                               "sample": f"{done} rows x {prob.n} columns ({entries:.3g} entries, {dt:.1f} s)"}}
 
 
-def batch_mode(args) -> int:
+def run_batch(log=True) -> dict:
     """64 grid problems with sides drawn from {32, 64, 128, 256} (seed 41), each
     solved to a 1% relative gap: one after another with bdrs_solve, then all at
     once with bdrs_batch_solve (captured 50-iteration blocks).  Solver set-up
@@ -141,7 +143,8 @@ def batch_mode(args) -> int:
     data = [(t(p.x, torch.float32), t(p.y, torch.float32), t(p.r, torch.float64), t(p.c, torch.float64),
              p.cost_scale) for p in probs]
     cap, tau = 40000, 0.01
-    print(f"[bench] batch of {len(probs)} grids, sides {sorted(set(sides))}, eta={ETA}", flush=True)
+    if log:
+        print(f"[bench] batch of {len(probs)} grids, sides {sorted(set(sides))}, eta={ETA}", flush=True)
     # warm-up of every kernel variant
     w = bdrs.Solver(*data[0][:4], data[0][4], eta=ETA)
     w.solve(tau, 100, CERT_EVERY)
@@ -157,53 +160,63 @@ def batch_mode(args) -> int:
         seq_t += time.perf_counter() - t0
         seq.append((ok, ce))
         sv.close()
-        if (i + 1) % 8 == 0:
-            print(f"[bench] sequential: {i + 1} solved, {seq_t:.2f} s", flush=True)
-    print(f"[bench] sequential: {seq_t:.2f} s", flush=True)
+        if log and (i + 1) % 16 == 0:
+            print(f"[bench] batch workload, sequential: {i + 1} solved, {seq_t:.2f} s", flush=True)
     svs = [bdrs.Solver(*d[:4], d[4], eta=ETA) for d in data]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st, certs, sts = bdrs.batch_solve(svs, tau, cap, CERT_EVERY, use_graph=True)
     torch.cuda.synchronize()
     bat_t = time.perf_counter() - t0
+    for sv in svs:
+        sv.close()
     same = all(c["k"] == s[1]["k"] and c["U"] == s[1]["U"] and c["L"] == s[1]["L"] for c, s in zip(certs, seq))
     reached = sum(1 for x in sts if x == bdrs.OK)
     entries = sum(2.0 * p.m * p.n * (c["k"] + 1) for p, c in zip(probs, certs))
+    out = {"makespan_s": round(bat_t, 3), "sequential_s": round(seq_t, 3),
+           "speedup_vs_sequential": round(seq_t / bat_t, 4),
+           "batched_gentries_per_s": round(entries / bat_t / 1e9, 1),
+           "sequential_gentries_per_s": round(entries / seq_t / 1e9, 1),
+           "reached": reached, "problems": len(probs), "bitwise_equal_alone_vs_batched": bool(same),
+           "workload": "64 grid histogram pairs, sides from {32,64,128,256} (seed 41), seeds (4100+2p, 4101+2p), "
+                       f"eta {ETA}, 1% relative gap, cap {cap}",
+           "iterations": {str(s): sorted(set(c["k"] + 1 for c, sd in zip(certs, sides) if sd == s))
+                          for s in sorted(set(sides))}}
+    if log:
+        print(f"[bench] batch: {out['makespan_s']} s batched vs {out['sequential_s']} s sequential "
+              f"({out['speedup_vs_sequential']}x), {reached}/{len(probs)} reached, bitwise {same}", flush=True)
+    return out
+
+
+def batch_mode(args) -> int:
+    out = run_batch()
     line = {
-        "metric": "makespan of 64 uneven grid OT solves to 1% relative gap", "value": round(bat_t, 3),
+        "metric": "makespan of 64 uneven grid OT solves to 1% relative gap", "value": out["makespan_s"],
         "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "64 grid histogram pairs, sides from {32,64,128,256} (seed 41), "
-                               "seeds (4100+2p, 4101+2p)", "eta": ETA, "lambda": 1.0,
-                   "cert_every": CERT_EVERY, "cap": cap},
-        "sequential_s": round(seq_t, 3), "speedup_vs_sequential": round(seq_t / bat_t, 4),
-        "batched_gentries_per_s": round(entries / bat_t / 1e9, 1),
-        "sequential_gentries_per_s": round(entries / seq_t / 1e9, 1),
-        "reached": reached, "bitwise_equal_alone_vs_batched": bool(same),
-        "iterations": {str(s): sorted(set(c["k"] + 1 for c, sd in zip(certs, sides) if sd == s))
-                       for s in sorted(set(sides))},
+        "config": {"workload": out["workload"], "eta": ETA, "lambda": 1.0, "cert_every": CERT_EVERY},
+        **{k: v for k, v in out.items() if k not in ("makespan_s", "workload")},
     }
     print(json.dumps(line), flush=True)
     return 0
 
 
-def serve_mode(args) -> int:
-    """Poisson arrivals of grid OT requests (sides from --serve-sides, default
-    {32, 64, 128}, drawn with seed 52; inter-arrival gaps with seed 51; request q seeds (5100+2q, 5101+2q)),
+def run_serve(n_req: int, menu: list, load: float, plain: bool = False, log=True) -> dict:
+    """Poisson arrivals of grid OT requests (sides from `menu`, drawn with seed
+    52; inter-arrival gaps with seed 51; request q seeds (5100+2q, 5101+2q)),
     each stopped at a 1% relative gap.  The arrival rate is `load` times the
     sequential capacity measured on a sample.  The same arrival schedule is
     served twice: one request at a time (FIFO) and with continuous batching
     (up to 32 running requests in a 1 GiB pool, requests above BIG_WORK
-    entries per sweep one at a time)."""
+    entries per sweep one at a time).  Latency = completion - submission,
+    including the host preparation of the request and its upload."""
     import threading
     import numpy as np
-    import torch
     from paper_2609_33814_amd import bdrs, inputs
-    n_req = args.requests
-    menu = [int(v) for v in args.serve_sides.split(",")]
     sides = [menu[i] for i in np.random.default_rng(52).integers(0, len(menu), n_req)]
     probs = [inputs.grid_problem(s, 5100 + 2 * q, 5101 + 2 * q) for q, s in enumerate(sides)]
     tau, cap, block, pool = 0.01, 20000, CERT_EVERY, 1 << 30
-    print(f"[bench] serve: {n_req} requests, sides {menu}, eta={ETA}, pool {pool >> 20} MiB", flush=True)
+    if log:
+        print(f"[bench] serve: {n_req} requests, sides {menu}, eta={ETA}, pool {pool >> 20} MiB", flush=True)
 
     # sequential capacity from a sample of requests served alone
     calib = bdrs.Server(pool, 1, block)
@@ -213,10 +226,11 @@ def serve_mode(args) -> int:
         calib.wait(calib.submit(p, eta=ETA, tau=tau, max_iters=cap))
     mean_s = (time.perf_counter() - t0) / len(sample)
     calib.close()
-    rate = args.load / mean_s
+    rate = load / mean_s
     gaps = np.random.default_rng(51).exponential(1.0 / rate, n_req)
     arrivals = np.cumsum(gaps) - gaps[0]
-    print(f"[bench] sequential capacity {1 / mean_s:.2f} solves/s; arrival rate {rate:.2f}/s", flush=True)
+    if log:
+        print(f"[bench] serve: sequential capacity {1 / mean_s:.2f} solves/s; arrival rate {rate:.2f}/s", flush=True)
 
     def run(max_slots, big_work=0.0):
         srv = bdrs.Server(pool, max_slots, block)
@@ -230,47 +244,45 @@ def serve_mode(args) -> int:
                 if delay > 0:
                     time.sleep(delay)
                 tickets[q] = srv.submit(probs[q], eta=ETA, tau=tau, max_iters=cap)
-                if (q + 1) % 16 == 0:
-                    print(f"[bench]   max_slots={max_slots}: {q + 1} submitted at "
-                          f"{time.perf_counter() - start:.1f} s", flush=True)
 
         th = threading.Thread(target=feeder)
         th.start()
         th.join()
-        res = []
-        for q, t in enumerate(tickets):
-            res.append(srv.wait(t))
-            if (q + 1) % 16 == 0:
-                print(f"[bench]   max_slots={max_slots}: {q + 1} done at {time.perf_counter() - start:.1f} s",
-                      flush=True)
+        res = [srv.wait(t) for t in tickets]
         srv.close()
         lat = np.array([r["t_done"] - r["t_submit"] for r in res])
         span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
         ok = sum(1 for r in res if r["status"] == bdrs.OK)
-        return dict(p50_s=round(float(np.percentile(lat, 50)), 4), p99_s=round(float(np.percentile(lat, 99)), 4),
-                    mean_s=round(float(lat.mean()), 4), solves_per_s=round(n_req / span, 3), reached=ok), res
+        out = dict(p50_s=round(float(np.percentile(lat, 50)), 4), p99_s=round(float(np.percentile(lat, 99)), 4),
+                   mean_s=round(float(lat.mean()), 4), solves_per_s=round(n_req / span, 3), reached=ok)
+        if log:
+            print(f"[bench] serve, max_slots={max_slots}: {out}", flush=True)
+        return out, res
 
     fifo, res_f = run(1)
-    print(f"[bench] FIFO one at a time: {fifo}", flush=True)
     cont, res_c = run(32, BIG_WORK)
-    print(f"[bench] continuous batching: {cont}", flush=True)
-    same = all(a["cert"]["k"] == b["cert"]["k"] and a["cert"]["U"] == b["cert"]["U"] for a, b in zip(res_f, res_c))
-    plain = None
-    if args.serve_plain:
-        plain, _ = run(32, 0.0)
-        print(f"[bench] continuous batching, arrival-order admission: {plain}", flush=True)
+    same = all(a["cert"]["k"] == b["cert"]["k"] and a["cert"]["U"] == b["cert"]["U"] and
+               a["cert"]["L"] == b["cert"]["L"] for a, b in zip(res_f, res_c))
+    plain_out = run(32, 0.0)[0] if plain else None
+    return {"continuous_batching": cont, "fifo_sequential": fifo, "continuous_batching_arrival_order": plain_out,
+            "p99_speedup": round(fifo["p99_s"] / cont["p99_s"], 3),
+            "p50_speedup": round(fifo["p50_s"] / cont["p50_s"], 3),
+            "results_equal_fifo_vs_batched": bool(same), "requests": n_req,
+            "workload": f"{n_req} grid requests, sides from {menu} (seed 52), arrivals Exp (seed 51) at "
+                        f"{load} x sequential capacity, eta {ETA}, 1% relative gap",
+            "block_iters": block, "pool_MiB": pool >> 20, "max_slots": 32, "big_work": BIG_WORK}
+
+
+def serve_mode(args) -> int:
+    menu = [int(v) for v in args.serve_sides.split(",")]
+    out = run_serve(args.requests, menu, args.load, plain=args.serve_plain)
     line = {
         "metric": "p50/p99 latency of OT solve requests to 1% relative gap (Poisson arrivals)",
-        "value": cont["p99_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"{n_req} grid requests, sides from {menu} (seed 52), arrivals Exp (seed 51) at "
-                               f"{args.load} x sequential capacity", "eta": ETA, "lambda": 1.0,
-                   "block_iters": block, "pool_MiB": pool >> 20, "max_slots": 32,
-                   "big_work": BIG_WORK},
-        "continuous_batching": cont, "fifo_sequential": fifo,
-        "continuous_batching_arrival_order": plain,
-        "p99_speedup": round(fifo["p99_s"] / cont["p99_s"], 3),
-        "results_equal_fifo_vs_batched": bool(same),
+        "value": out["continuous_batching"]["p99_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": out["workload"], "eta": ETA, "lambda": 1.0, "block_iters": out["block_iters"],
+                   "pool_MiB": out["pool_MiB"], "max_slots": 32, "big_work": BIG_WORK},
+        **{k: v for k, v in out.items() if k not in ("workload", "block_iters", "pool_MiB", "max_slots", "big_work")},
     }
     print(json.dumps(line), flush=True)
     return 0
@@ -532,6 +544,10 @@ def main() -> int:
     ap.add_argument("--lam", type=float, default=1.0)
     ap.add_argument("--no-ttg", action="store_true", help="skip the time-to-1%% runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch (makespan vs sequential)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serve run (p50/p99 vs FIFO)")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests of the default run's serve measurement (sides 32, 64, 128)")
     ap.add_argument("--ttg-cap", type=int, default=20000)
     ap.add_argument("--mode", choices=("sweep", "batch", "serve", "colour", "colour10m", "ablation", "export"),
                     default="sweep",
@@ -629,18 +645,31 @@ def main() -> int:
     ttg = {}
     if not args.no_ttg:
         for lam in (1.0, 1.2, 1.5, 1.99):
+            # the clock starts with the inputs resident: solver creation (workspace,
+            # validation, tile order, upload) is inside, data generation outside
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             s2 = bdrs.Solver(X, Y, R, C, prob.cost_scale, eta=ETA, lam=lam)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             ok, ce = s2.solve(0.01, args.ttg_cap, CERT_EVERY)
             torch.cuda.synchronize()
-            dt = time.perf_counter() - t1
-            ttg[f"lambda={lam}"] = {"reached": bool(ok), "seconds": round(dt, 4),
-                                    "iterations": int(ce["k"]) + 1,
+            t2 = time.perf_counter()
+            iters = int(ce["k"]) + 1
+            ttg[f"lambda={lam}"] = {"reached": bool(ok), "seconds": round(t2 - t0, 4),
+                                    "seconds_create": round(t1 - t0, 4), "seconds_solve": round(t2 - t1, 4),
+                                    "iterations": iters,
+                                    "whole_solve_gentries_per_s": round(2.0 * prob.m * prob.n * iters / (t2 - t0) / 1e9,
+                                                                         1),
                                     "rel_gap_best": ce["rel_gap_best"],
                                     "U_best": ce["U_best"], "L_best": ce["L_best"]}
             print(f"[bench] time-to-1% lambda={lam}: {ttg[f'lambda={lam}']}", flush=True)
             s2.close()
+
+    batch = None if args.no_batch else run_batch()
+    serve = None
+    if not args.no_serve:
+        serve = run_serve(args.serve_requests, [32, 64, 128], 0.8)
 
     if args.calib_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)   # 256 MiB
@@ -660,6 +689,12 @@ def main() -> int:
                                "n=m=16384, d=2, sq. Euclidean cost scaled to max 1",
                    "eta": ETA, "lambda": args.lam, "cert_every": CERT_EVERY,
                    "step": "50 iterations (100 sweeps) + fused certificate",
+                   "timed_window": {"k_first": args.warmup * CERT_EVERY,
+                                    "k_last": (args.warmup + args.steps) * CERT_EVERY - 1,
+                                    "evaluated_fraction": round(evaluated_frac, 4),
+                                    "note": "value counts implicit entries m n per sweep; the sweeps "
+                                            "evaluate the fraction above (the rest lies below 2^-T of "
+                                            "each output's maximum and is skipped)"},
                    "last_rel_gap": last["rel_gap"] if last else None},
         "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 2),
                      "unit": "Gentries/s", "frac": round(achieved / peak, 4),
@@ -672,6 +707,8 @@ def main() -> int:
                      "counters": profiled_counters(splits_row)},
         "cpu_baseline": cpu,
         "time_to_1pct": ttg,
+        "batch": batch,
+        "serve": serve,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -514,8 +514,10 @@ BDRS_API bdrs_status bdrs_profile_read(bdrs_solver s, int64_t *sweeps, double *m
                                        double *entries);
 /* Entries the timed sweeps actually evaluated since the last enable: a sweep
  * skips an input tile for a wavefront of 64 outputs when its bound puts
- * every term of the tile below 2^-64 of each output's running maximum (such
- * terms cannot change a float32 sum), so this can be far below the implicit
+ * every term of the tile below 2^-T of each output's running maximum, with
+ * T = 30 + ceil(log2 n_in) (at most 64) for n_in inputs (all skipped terms
+ * of an output together stay below 2^-30 of its sum, under float32's
+ * rounding), so this can be far below the implicit
  * m n per sweep late in a solve.  Counted per (64 outputs, 64 inputs) pair,
  * padding included.  Synchronises the stream. */
 BDRS_API bdrs_status bdrs_profile_evaluated(bdrs_solver s, double *entries);

@@ -42,7 +42,7 @@ struct Ctrl {
 // Everything the sweep needs to know about one input tile besides the offsets
 // and weights of its points, read with a single 64-byte scalar load.
 struct alignas(64) TileRec {
-  double amax;    // tile maximum of the absolute log2 weights (float64; -inf: no mass)
+  double amax;    // tile maximum of w2 - kappa2 |b|^2 (float64; -inf: no mass)
   double alpha;   // intercept of the plane fit of the tile's log2 weights w2 over the
                   // offsets b: w2 <= alpha + gamma . b + rho for every point of the tile
   float ctr[3];   // tile centre (relative to the common origin)
@@ -62,8 +62,8 @@ struct SideDev {
   int pad;
   float* abs;      // [dim][np] coordinates relative to the common origin (SoA)
   float* off;      // [ntiles][dim][64] offsets from the tile centre
-  float* A;        // [np] log2 weights of the next sweep that reads this side, relative
-                   //      to their tile maximum (small magnitudes, float32)
+  float* A;        // [np] log2 weights of the next sweep that reads this side minus their
+                   //      tile's plane fit and the tile-local quadratic (float32)
   TileRec* tile;   // [ntiles] per-tile record (maximum, plane fit, centre, radius)
   int* perm;       // [np] original index of each slot
   int* iperm;      // [count] slot of each original index

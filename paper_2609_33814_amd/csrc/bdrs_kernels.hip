@@ -7,18 +7,25 @@
 //     kappa2 = log2(e) * s / eps,   w2 = log2(e) * w,
 // which is LSE_q(w_q - C_pq / eps) / ln 2.  The cost is never stored: inputs
 // are grouped in tiles of 64 spatially close points with centre Qc, offsets
-// b_q = Q_q - Qc, and with a = P_p - Qc the exponent expands exactly as
-//     w2_q - kappa2 |a - b_q|^2 = A_q + (2 kappa2 a) . b_q - kappa2 |a|^2,
-//     A_q = w2_q - kappa2 |b_q|^2   (written by the producing epilogue),
+// b_q = Q_q - Qc, and with a = P_p - Qc and the plane fit
+// w2_q ~ alpha + gamma . b_q of the tile's weights the exponent expands
+// exactly as
+//     w2_q - kappa2 |a - b_q|^2 = base + B . b_q + A_q,
+//     base = alpha - kappa2 |a|^2,  B = gamma + 2 kappa2 a,
+//     A_q = w2_q - alpha - gamma . b_q - kappa2 |b_q|^2   (written by the producing epilogue),
 // i.e. d FMAs and one add per entry, then one v_exp_f32 and one add.
 //
 // Precision split.  The weights w grow like g / eps as the temperature falls,
 // so float32 values of that size would carry absolute errors u |g| / eps.  The
-// inner loop therefore only sees small numbers: A_q is stored relative to its
-// tile maximum, A'_q = A_q - Amax_t (float32), and the large per-(output, tile)
-// part base = Amax_t - kappa2 |a|^2 and the lane's running shift M are kept in
-// float64.  The summand is 2^{cm + B . b_q + A'_q} with cm = base - M (float32,
-// small for the tiles that dominate the sum).
+// inner loop therefore only sees small numbers: A_q is the weight's residual
+// from its tile's plane minus the tile-local quadratic (float32), B is formed
+// in float64 before it is rounded, and the large per-(output, tile) part base
+// and the lane's running shift M are kept in float64.  The summand is
+// 2^{cm + B . b_q + A_q} with cm = base - M (float32).  For the entries that
+// dominate an output's sum B is the exponent's slope across the tile near its
+// maximum, so every float32 operand is of the order of kappa2 r^2 (r the tile
+// radius) rather than of the weights' variation across the tile, which at low
+// temperature is 2 kappa2 |a| r, the transport distance |a| times larger.
 //
 // Stability without a per-entry max: the per-(output, tile) upper bound
 //     UB = base + sum_d |2 kappa2 a_d| rad_d  >=  max_q exponent
@@ -46,7 +53,18 @@ namespace {
 
 constexpr double kLog2eD = 1.4426950408889634074;
 constexpr double kLn2D = 0.69314718055994530942;
+// Exact-max gate: a tile whose bound exceeds the running shift by more than
+// this takes its exact maximum first, so no summed term exceeds 2^64.
 constexpr float kThresh = 64.0f;
+
+// Skip gate of a sweep over n inputs: a tile whose bound lies more than
+// T = 30 + ceil(log2 n) (at most 64) below an output's running shift M is
+// skipped.  Every output's sum is at least 2^M (the term that set M is
+// summed), and the skipped terms add at most n 2^{M-T} <= 2^{M-30}: 1/64 of
+// float32's half-ulp, below the rounding of the float32 sum itself.
+__device__ __forceinline__ double skip_threshold(int n) {
+  return fmin(64.0, 30.0 + ceil(log2((double)max(n, 1))));
+}
 
 template <typename CtrlPtr>
 __device__ __forceinline__ double eps_of(CtrlPtr c, double eps_arg, int kshift) {
@@ -170,7 +188,7 @@ __device__ __forceinline__ Group<D> load_group(gfloat* __restrict__ offs_t, gflo
 // (every nsplit-th tile).  Per chunk of up to 64 tiles a coarse test against
 // the wavefront's output box picks the candidate tiles; per candidate the lane
 // bounds its own exponents and the wavefront skips the tile when no lane can
-// see it, else every lane evaluates z_q = cm + B . b_q + A'_q and accumulates
+// see it, else every lane evaluates z_q = cm + B . b_q + A_q and accumulates
 // exp2(z_q) (and, for the certificate, the cost-weighted sum).  The next group
 // of 8 points (after a tile's last group, the next candidate's first) is
 // requested before the current group is computed, so the loads overlap the
@@ -199,7 +217,7 @@ __device__ __forceinline__ void sweep_block(
   const int j_hint = hint[p];
   const double eps = row_sweep ? eps_row_of(ctrl, eps_arg, kofs) : eps_of(ctrl, eps_arg, kofs);
   const double kap2d = kLog2eD * ctrl->scale / eps;
-  const float kap2x2 = (float)(2.0 * kap2d);
+  const double kap2x2d = 2.0 * kap2d;
   const float kap2f = (float)kap2d;
   const float inv2kap = (float)(0.5 / kap2d);
 
@@ -252,18 +270,19 @@ __device__ __forceinline__ void sweep_block(
     const int j = j_hint;
     const int jc = min(max(j, 0), count_in - 1);
     const int tj = jc / kTile, qj = jc % kTile;
-    const double am = in_tile[tj].amax;
+    const double al = in_tile[tj].alpha;
     const float aj = in_A[jc];
-    double na = 0.0, ab = 0.0;
+    double na = 0.0, ab = 0.0, gb = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const double ad = (double)P[d] - (double)in_tile[tj].ctr[d];
       const double bd = (double)in_off[((size_t)tj * D + d) * kTile + qj];
       na += ad * ad;
       ab += ad * bd;
+      gb += (double)in_tile[tj].gam[d] * bd;
     }
-    if (j >= 0 && j < count_in && am > -INFINITY && aj > -INFINITY) {
-      M = am + (double)aj + kap2d * (2.0 * ab - na);
+    if (j >= 0 && j < count_in && al > -INFINITY && aj > -INFINITY) {
+      M = al + (double)aj + gb + kap2d * (2.0 * ab - na);
       J = j;
     }
   }
@@ -285,8 +304,9 @@ __device__ __forceinline__ void sweep_block(
     return;
   }
 
+  const double tskip = skip_threshold(count_in);
   double Mth = M + kThresh;                     // the exact-max gate, updated with M
-  double Mlo = M - kThresh;                     // the skip gate, updated with M
+  double Mlo = M - tskip;                       // the skip gate, updated with M
   // The weights are read with broadcast vector loads (a lane-dependent zero in
   // the address), which leaves the scalar path to the offsets and the
   // candidates' tile records: moving either kind the other way measured slower.
@@ -310,14 +330,9 @@ __device__ __forceinline__ void sweep_block(
       gfloat* __restrict__ a_t = in_A + (size_t)t * kTile + lane0;
       gfloat* __restrict__ offs_n = in_off + (size_t)tn * D * kTile;
       gfloat* __restrict__ a_n = in_A + (size_t)tn * kTile + lane0;
-      float a[D], B[D], na = 0.0f;
+      float a[D];
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        a[d] = P[d] - cur.ctr[d];
-        na = fmaf(a[d], a[d], na);
-        B[d] = kap2x2 * a[d];
-      }
-      const double base = cur.amax - kap2d * (double)na;  // Amax_t - kappa2 |a|^2
+      for (int d = 0; d < D; ++d) a[d] = P[d] - cur.ctr[d];
       // upper bound of the exponents w2_q - kappa2 |a - b_q|^2 of this tile:
       // w2_q <= alpha + gamma . b_q + rho, and the concave quadratic
       // gamma . b - kappa2 |a - b|^2 is maximised over the tile's box per axis
@@ -331,7 +346,7 @@ __device__ __forceinline__ void sweep_block(
         ubf = fmaf(-kap2f, df * df, ubf);
       }
       const double ub = cur.alpha + (double)ubf;
-      // every term of this tile lies below 2^-64 of the running maximum on every
+      // every term of this tile lies below 2^-T of the running maximum on every
       // lane: the tile cannot change any sum in float32, so it is skipped.  A
       // tile without mass (alpha = -inf) is skipped here once M is finite, and
       // by its maximum below; testing the maximum first would make every tile
@@ -342,6 +357,13 @@ __device__ __forceinline__ void sweep_block(
         continue;
       }
       ++evaluated;
+      float B[D], na = 0.0f;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        na = fmaf(a[d], a[d], na);
+        B[d] = (float)fma(kap2x2d, (double)a[d], (double)cur.gam[d]);  // gamma + 2 kappa2 a, rounded once
+      }
+      const double base = cur.alpha - kap2d * (double)na;  // alpha_t - kappa2 |a|^2
 
       if (ub > Mth) {
         // exact maximum of this tile for the lanes whose bound exceeds the window
@@ -370,7 +392,7 @@ __device__ __forceinline__ void sweep_block(
           }
           M = tmd;
           Mth = M + kThresh;
-          Mlo = M - kThresh;
+          Mlo = M - tskip;
           J = t * kTile + qi;
         }
       }
@@ -538,12 +560,16 @@ __device__ __forceinline__ Merged merge_splits(const PartialRec* __restrict__ pa
   return r;
 }
 
-// A_p = log2(e) w - kappa2 |b_p|^2 in float64 (-inf on padding or for w = -inf);
-// stores the tile maximum (float64) and A_p minus that maximum (float32), and
-// a plane fit w2 ~ alpha + gamma . b of the tile's log2 weights w2 = log2(e) w
-// with its largest residual rho (so w2 <= alpha + gamma . b + rho holds for
-// every point of the tile, whatever the fit).  The sweep turns it into an
-// upper bound of its exponents.  Called by whole wavefronts (one tile each).
+// Packs the weights w of one tile for the sweeps: a least-squares plane
+// w2 ~ alpha + gamma . b of the tile's log2 weights w2 = log2(e) w over the
+// offsets b, with its largest residual rho (so w2 <= alpha + gamma . b + rho
+// holds for every point of the tile, whatever the fit: the sweep turns it
+// into an upper bound of its exponents), and per point
+// A_p = w2_p - alpha - gamma . b_p - kappa2 |b_p|^2 in float32 (-inf on padding
+// or for w = -inf), the part of the exponent that does not depend on the
+// output.  The record also holds the tile maximum of w2 - kappa2 |b|^2
+// (float64; -inf when the tile has no mass).  Called by whole wavefronts (one
+// tile each).
 // Offsets of point p from its tile centre (0 past the real points); the
 // epilogues request them before they wait for the split records.
 // Three loads at clamped (valid) addresses whatever dim and p are, zeroed by a
@@ -578,7 +604,6 @@ __device__ __forceinline__ void pack_weight_d(const SideDev& sd, int p, double w
   }
   if (p >= sd.ntiles * kTile) return;
   const double m = wave_max(A);
-  sd.A[p] = (A == -INFINITY) ? -INFINITY : (float)(A - m);
   // least-squares plane through the live points of the tile (centred sums)
   const double one = live ? 1.0 : 0.0;
   const double cnt = wave_sum(one);
@@ -633,6 +658,8 @@ __device__ __forceinline__ void pack_weight_d(const SideDev& sd, int p, double w
     res = w2 - alpha;
     for (int d = 0; d < dim; ++d) res -= gam[d] * b[d];
   }
+  // the weight's residual from the plane minus the tile-local quadratic
+  sd.A[p] = live ? (float)(res - kap2 * (double)n2) : -INFINITY;
   const double rho = wave_max(fabs(res));
   if ((threadIdx.x & (kTile - 1)) == 0) {
     TileRec& tr = sd.tile[t];
