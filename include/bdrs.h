@@ -389,6 +389,28 @@ BDRS_API bdrs_status bdrs_batch_solve(const bdrs_solver *solvers, int32_t count,
                                       bdrs_cert *outs, int32_t *statuses);
 
 /*
+ * Batched solving for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation):
+ * bdrs_batch_solve without its workspace argument and with use_graph = 0.
+ * The descriptors, work lists and certificate records live in a device array
+ * of BDRS_BATCH_STATIC_BYTES that the library holds on every GPU it runs on
+ * until the process ends, and the blocks are launched one by one on the
+ * first solver's stream.  The call allocates no device memory and creates no
+ * stream, event or graph; each solver's own workspace is the caller's, as
+ * always.  Results are bitwise those of bdrs_batch_solve.  BDRS_E_NOMEM when
+ * bdrs_batch_workspace_size of the solvers exceeds BDRS_BATCH_STATIC_BYTES
+ * (checked on the host before any device work); other errors as
+ * bdrs_batch_solve.  Every call on a GPU shares that GPU's array, which keeps
+ * the last call's contents (each call writes all it reads): calls that
+ * overlap on one GPU, from several threads, race and must be serialised by
+ * the caller.  Synchronous.
+ */
+#define BDRS_BATCH_STATIC_BYTES (16u << 20)
+BDRS_API bdrs_status bdrs_batch_solve_static(const bdrs_solver *solvers, int32_t count, double tau,
+                                             int32_t tau_relative, int32_t max_iters, int32_t cert_every,
+                                             bdrs_cert *outs, int32_t *statuses);
+
+/*
  * Solve server: continuous batching of independent OT solves on one GPU.
  * The server owns a device memory pool given by the caller (the "HBM
  * budget"); every admitted request gets its workspace (bdrs_workspace_size of

@@ -40,8 +40,9 @@ EXPORTS = [
     "bdrs_get_hints", "bdrs_set_hints", "bdrs_autotune_workspace_size", "bdrs_autotune",
     "bdrs_tune_set", "bdrs_tune_get", "bdrs_tune_clear", "bdrs_plan", "bdrs_server_set_policy",
     "bdrs_round", "bdrs_profile_evaluated", "bdrs_restore_best", "bdrs_export_plan",
-    "bdrs_plan_entries",
+    "bdrs_plan_entries", "bdrs_batch_solve_static",
 ]
+BATCH_STATIC_BYTES = 16 << 20   # BDRS_BATCH_STATIC_BYTES
 
 PLAN_ROUNDED = 0
 PLAN_REPAIRED = 1
@@ -178,6 +179,8 @@ def lib() -> ctypes.CDLL:
         L.bdrs_batch_solve.argtypes = [P(vp), ctypes.c_int32, vp, ctypes.c_size_t, ctypes.c_double,
                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        P(Cert), P(ctypes.c_int32)]
+        L.bdrs_batch_solve_static.argtypes = [P(vp), ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.c_int32, P(Cert), P(ctypes.c_int32)]
         L.bdrs_profile_read.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_double), P(ctypes.c_double)]
         L.bdrs_server_create.argtypes = [vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, P(vp)]
         L.bdrs_server_submit.argtypes = [vp, P(Request), P(ctypes.c_uint64)]
@@ -450,6 +453,22 @@ def batch_solve(solvers, tau: float, max_iters: int, cert_every: int, relative: 
                                 int(max_iters), int(cert_every), 1 if use_graph else 0, outs, sts)
     check(st, allow=(OK, NOT_CONVERGED))
     del ws
+    return st, [o.as_dict() for o in outs], list(sts)
+
+
+def batch_solve_static(solvers, tau: float, max_iters: int, cert_every: int, relative: bool = True):
+    """bdrs_batch_solve_static: the batched solve with the library's static
+    device array for its work lists (no workspace, no allocation).
+
+    Returns (status, [cert dict per solver], [status per solver]).
+    """
+    n = len(solvers)
+    arr = (ctypes.c_void_p * n)(*[s.handle.value for s in solvers])
+    outs = (Cert * n)()
+    sts = (ctypes.c_int32 * n)()
+    st = lib().bdrs_batch_solve_static(arr, n, float(tau), 1 if relative else 0, int(max_iters),
+                                       int(cert_every), outs, sts)
+    check(st, allow=(OK, NOT_CONVERGED))
     return st, [o.as_dict() for o in outs], list(sts)
 
 

@@ -12,6 +12,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -692,9 +694,14 @@ bdrs_status bdrs_batch_workspace_size(const bdrs_solver* solvers, int32_t count,
   return BDRS_OK;
 }
 
-bdrs_status bdrs_batch_solve(const bdrs_solver* solvers, int32_t count, void* workspace, size_t workspace_bytes,
-                             double tau, int32_t tau_relative, int32_t max_iters, int32_t cert_every,
-                             int32_t use_graph, bdrs_cert* outs, int32_t* statuses) {
+}  // extern "C"
+
+namespace bdrs_host {
+
+// Host checks shared by the batched entry points (no device work except
+// reading each solver's iteration counter); need: the work-list bytes.
+bdrs_status check_batch_call(const bdrs_solver* solvers, int32_t count, double tau, int32_t max_iters,
+                             int32_t cert_every, const bdrs_cert* outs, const int32_t* statuses, size_t* need) {
   bdrs_status st = check_batch(solvers, count);
   if (st != BDRS_OK) return st;
   if (!outs || !statuses) return fail(BDRS_E_INVALID, "outs and statuses are required");
@@ -702,12 +709,12 @@ bdrs_status bdrs_batch_solve(const bdrs_solver* solvers, int32_t count, void* wo
   if (cert_every < 1) return fail(BDRS_E_INVALID, "cert_every must be >= 1");
   if (max_iters < 1 || max_iters % cert_every)
     return fail(BDRS_E_INVALID, "max_iters must be a positive multiple of cert_every");
-  if (!workspace || ((uintptr_t)workspace) % kAlign)
-    return fail(BDRS_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
-  std::vector<bdrs_solver> all(solvers, solvers + count);
-  const size_t need = BatchEngine::bytes_for(all);
-  if (workspace_bytes < need)
-    return fail(BDRS_E_NOMEM, "batch workspace too small: %zu bytes given, %zu needed", workspace_bytes, need);
+  *need = BatchEngine::bytes_for(std::vector<bdrs_solver>(solvers, solvers + count));
+  return BDRS_OK;
+}
+
+bdrs_status check_batch_members(const bdrs_solver* solvers, int32_t count, int32_t cert_every) {
+  bdrs_status st;
   for (int i = 0; i < count; ++i) {
     if ((st = sync_k(solvers[i])) != BDRS_OK) return st;
     if (solvers[i]->k % cert_every)
@@ -719,8 +726,15 @@ bdrs_status bdrs_batch_solve(const bdrs_solver* solvers, int32_t count, void* wo
     if (solvers[i]->L.keep_best)
       return fail(BDRS_E_INVALID, "solvers[%d]: BDRS_F_KEEP_BEST_STATE is not supported in batches", i);
   }
-  hipStream_t st_b = nullptr;
-  HIPCHK(hipStreamCreateWithFlags(&st_b, hipStreamNonBlocking));
+  return BDRS_OK;
+}
+
+// The block loop of a batched solve on stream st_b with the work lists in ws;
+// synchronises st_b before it returns.
+bdrs_status run_batch(const bdrs_solver* solvers, int32_t count, char* ws, double tau, int32_t tau_relative,
+                      int32_t max_iters, int32_t cert_every, bool use_graph, hipStream_t st_b, bdrs_cert* outs,
+                      int32_t* statuses) {
+  std::vector<bdrs_solver> all(solvers, solvers + count);
   std::vector<int> index(count), done_iters(count, 0);
   for (int i = 0; i < count; ++i) {
     index[i] = i;
@@ -731,7 +745,7 @@ bdrs_status bdrs_batch_solve(const bdrs_solver* solvers, int32_t count, void* wo
   hipError_t e;
   {
     BatchEngine eng;
-    e = eng.bind(all, (char*)workspace, cert_every, use_graph != 0, st_b);
+    e = eng.bind(all, ws, cert_every, use_graph, st_b);
     std::vector<double> rec;
     while (e == hipSuccess && !active.empty()) {
       e = eng.run_block();
@@ -761,16 +775,82 @@ bdrs_status bdrs_batch_solve(const bdrs_solver* solvers, int32_t count, void* wo
         active.swap(still);
         std::vector<bdrs_solver> mem;
         for (int p : active) mem.push_back(solvers[p]);
-        e = eng.bind(mem, (char*)workspace, cert_every, use_graph != 0, st_b);
+        e = eng.bind(mem, ws, cert_every, use_graph, st_b);
       }
     }
   }
   const hipError_t es = hipStreamSynchronize(st_b);  // also reports a fault of the last block
   if (e == hipSuccess) e = es;
-  (void)hipStreamDestroy(st_b);
   if (e != hipSuccess) return fail(BDRS_E_DEVICE, "HIP error %s in batch solve", hipGetErrorString(e));
   for (int i = 0; i < count; ++i) solvers[i]->packed_rows = true;
   return result;
+}
+
+// Device storage of bdrs_batch_solve_static: one array on every GPU the
+// library runs on, held until the process ends.  In host code `scratch` only
+// stands in for the symbol; its address on a device comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address is handed to copies and kernels.
+static __device__ __align__(256) char scratch[BDRS_BATCH_STATIC_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_addr;  // device -> address of its `scratch`
+
+// Address of the current device's array (looked up on the first call there).
+bdrs_status static_scratch(char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it == g_scratch_addr.end()) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(BDRS_E_DEVICE, "HIP error %s taking the address of the static batch array on device %d",
+                  hipGetErrorString(e), dev);
+    it = g_scratch_addr.emplace(dev, (char*)ptr).first;
+  }
+  *out = it->second;
+  return BDRS_OK;
+}
+
+}  // namespace bdrs_host
+
+extern "C" {
+
+bdrs_status bdrs_batch_solve_static(const bdrs_solver* solvers, int32_t count, double tau, int32_t tau_relative,
+                                    int32_t max_iters, int32_t cert_every, bdrs_cert* outs, int32_t* statuses) {
+  size_t need = 0;
+  bdrs_status st = check_batch_call(solvers, count, tau, max_iters, cert_every, outs, statuses, &need);
+  if (st != BDRS_OK) return st;
+  if (need > (size_t)BDRS_BATCH_STATIC_BYTES)
+    return fail(BDRS_E_NOMEM, "the batch needs %zu bytes of work lists, the static array holds %zu", need,
+                (size_t)BDRS_BATCH_STATIC_BYTES);
+  if ((st = check_batch_members(solvers, count, cert_every)) != BDRS_OK) return st;
+  char* ws = nullptr;
+  if ((st = static_scratch(&ws)) != BDRS_OK) return st;
+  // the first solver's stream; no graph (instantiating one allocates)
+  return run_batch(solvers, count, ws, tau, tau_relative, max_iters, cert_every, false, solvers[0]->ctx.stream, outs,
+                   statuses);
+}
+
+bdrs_status bdrs_batch_solve(const bdrs_solver* solvers, int32_t count, void* workspace, size_t workspace_bytes,
+                             double tau, int32_t tau_relative, int32_t max_iters, int32_t cert_every,
+                             int32_t use_graph, bdrs_cert* outs, int32_t* statuses) {
+  size_t need = 0;
+  bdrs_status st = check_batch_call(solvers, count, tau, max_iters, cert_every, outs, statuses, &need);
+  if (st != BDRS_OK) return st;
+  if (!workspace || ((uintptr_t)workspace) % kAlign)
+    return fail(BDRS_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+  if (workspace_bytes < need)
+    return fail(BDRS_E_NOMEM, "batch workspace too small: %zu bytes given, %zu needed", workspace_bytes, need);
+  if ((st = check_batch_members(solvers, count, cert_every)) != BDRS_OK) return st;
+  hipStream_t st_b = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&st_b, hipStreamNonBlocking));
+  st = run_batch(solvers, count, (char*)workspace, tau, tau_relative, max_iters, cert_every, use_graph != 0, st_b,
+                 outs, statuses);
+  (void)hipStreamDestroy(st_b);
+  return st;
 }
 
 const char* bdrs_last_error(void) { return g_err.c_str(); }

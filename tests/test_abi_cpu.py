@@ -257,3 +257,15 @@ def test_export_plan_rejects_null_solver_and_bad_kind():
     assert "NULL" in bdrs.last_error()
     assert L.bdrs_plan_entries(None, None, None, None, None, 1.0, 0, 0, None) == bdrs.E_INVALID
     assert bdrs.last_error()
+
+
+def test_static_batch_rejects_bad_arguments_on_host():
+    L = bdrs.lib()
+    ce = (bdrs.Cert * 2)()
+    sts = (ctypes.c_int32 * 2)()
+    assert L.bdrs_batch_solve_static(None, 1, 0.01, 1, 100, 50, ce, sts) == bdrs.E_INVALID
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert L.bdrs_batch_solve_static(arr, 0, 0.01, 1, 100, 50, ce, sts) == bdrs.E_INVALID
+    assert "count" in bdrs.last_error()
+    assert L.bdrs_batch_solve_static(arr, 2, 0.01, 1, 100, 50, ce, sts) == bdrs.E_INVALID
+    assert "NULL" in bdrs.last_error()
