@@ -222,8 +222,11 @@ def run_serve(n_req: int, menu: list, load: float, plain: bool = False, log=True
     calib = bdrs.Server(pool, 1, block)
     sample = probs[: min(16, n_req)]
     t0 = time.perf_counter()
-    for p in sample:
+    for q, p in enumerate(sample):
         calib.wait(calib.submit(p, eta=ETA, tau=tau, max_iters=cap))
+        if log and (q + 1) % 4 == 0:
+            print(f"[bench] serve calibration: {q + 1} of {len(sample)} alone, {time.perf_counter() - t0:.1f} s",
+                  flush=True)
     mean_s = (time.perf_counter() - t0) / len(sample)
     calib.close()
     rate = load / mean_s
@@ -248,7 +251,12 @@ def run_serve(n_req: int, menu: list, load: float, plain: bool = False, log=True
         th = threading.Thread(target=feeder)
         th.start()
         th.join()
-        res = [srv.wait(t) for t in tickets]
+        res = []
+        for q, tk in enumerate(tickets):
+            res.append(srv.wait(tk))
+            if log and (q + 1) % 8 == 0:
+                print(f"[bench] serve, max_slots={max_slots}: {q + 1} of {n_req} done at "
+                      f"{time.perf_counter() - start:.1f} s", flush=True)
         srv.close()
         lat = np.array([r["t_done"] - r["t_submit"] for r in res])
         span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)

@@ -111,6 +111,7 @@ Layout make_layout(int m, int n, int dim, int reserve_row, int reserve_col, bool
   L.plan_aux = take(sizeof(double) * L.R.np);
   L.plan_stats = take(sizeof(double) * kCertSlots);
   L.tile_total = take(sizeof(unsigned long long));
+  L.part_ref = take(sizeof(double) * (size_t)npmax);
   if (keep_best) {
     L.best_la = take(sizeof(double) * L.R.np);
     L.best_lah = take(sizeof(double) * L.R.np);
@@ -125,7 +126,7 @@ Layout make_layout(int m, int n, int dim, int reserve_row, int reserve_col, bool
   // partial records last: every other offset is independent of the split counts
   const size_t rows_rec = (size_t)std::max(L.splits_row, reserve_row) * L.R.np;
   const size_t cols_rec = (size_t)std::max(L.splits_col, reserve_col) * L.C.np;
-  L.part = take(sizeof(PartialRec) * std::max(rows_rec, cols_rec));
+  L.part = take((size_t)kPartialSlot * std::max(rows_rec, cols_rec));
   // one evaluated-tile count per (split, output wavefront) of a sweep (profiling)
   L.tile_count = take(sizeof(unsigned) * (std::max(rows_rec, cols_rec) / kTile));
   L.total = o;
@@ -311,7 +312,8 @@ void fill_ctx(bdrs_solver s) {
   c.st.mu = (double*)(base + L.mu);
   c.st.logs = (double*)(base + L.logs);
   c.st.pvec = (double*)(base + L.pvec);
-  c.part.rec = (PartialRec*)(base + L.part);
+  c.part.rec = (void*)(base + L.part);
+  c.part.ref = (double*)(base + L.part_ref);
   c.part.splits = L.splits_max;
   c.cert_part = (double*)(base + L.cert_part);
   c.cert_out = (double*)(base + L.cert_out);
@@ -586,10 +588,12 @@ hipError_t BatchEngine::bind(const std::vector<bdrs_solver>& members, char* ws, 
   for (int p = 0; p < (int)members_.size(); ++p) {
     const bdrs_solver s = members_[p];
     descs.push_back(s->ctx);
-    for (int sp = 0; sp < s->L.splits_row; ++sp)
-      for (int b = 0; b < s->L.R.np / kSweepBlock; ++b) rs.push_back({p, b, sp, 0});
-    for (int sp = 0; sp < s->L.splits_col; ++sp)
-      for (int b = 0; b < s->L.C.np / kSweepBlock; ++b) cs.push_back({p, b, sp, 0});
+    // split fastest: consecutive items go to consecutive XCDs, so an output
+    // block's splits spread over the XCDs (as in the single-problem launch)
+    for (int b = 0; b < s->L.R.np / kSweepBlock; ++b)
+      for (int sp = 0; sp < s->L.splits_row; ++sp) rs.push_back({p, b, sp, 0});
+    for (int b = 0; b < s->L.C.np / kSweepBlock; ++b)
+      for (int sp = 0; sp < s->L.splits_col; ++sp) cs.push_back({p, b, sp, 0});
     for (int t = 0; t < s->L.R.ntiles; ++t) rf.push_back({p, t, 0, 0});
     for (int t = 0; t < s->L.C.ntiles; ++t) cf.push_back({p, t, 0, 0});
     for (int b = 0; b < s->L.cert_blocks; ++b) ce.push_back({p, b, 0, 0});

@@ -86,24 +86,38 @@ struct StateDev {
   double* pvec;     // repair: row deficits p_i
 };
 
-// Partial reduction of one (split, output): shift M (log2, float64), shifted
-// sum S and shifted cost-weighted sum N (certificate sweeps), and the input
-// slot J that set M.  24 bytes.
+// Partial reduction of one (split, output) of a sweep.  dM is the split's
+// shift (log2) relative to the output's reference R (the exponent of its warm
+// start, the same in every split; 0 when there is none), kept in float32: the
+// sweep rescales its shifted sums by the rounding of dM, so that S 2^{R + dM}
+// is the split's sum to float32 accuracy.  S: shifted sum; J: input slot of
+// the term that set the shift (the warm start's unless an exact-max pass
+// raised it; -1 for none).  12 bytes; R is stored once per output.
 struct PartialRec {
-  double M;
-  float S, N;
-  int J;       // input slot of the exact maximum that set M, or -1
-  int pad;
+  float dM;
+  float S;
+  int J;
+};
+// The same for certificate sweeps, with the shifted cost-weighted sum N
+// (Algorithm 2's column statistics).  16 bytes.
+struct PartialCert {
+  float dM;
+  float S;
+  float N;
+  int J;
 };
 
-// Partial of the barycentric sweep (same 24-byte slot as PartialRec): shift M,
-// shifted sum S and the shifted sum of the input points' coordinates V.
+// Partial of the barycentric sweep: shift M (float64), shifted sum S and the
+// shifted sum of the input points' coordinates V.  24 bytes.
 struct PartialBary {
   double M;
   float S;
   float V[3];
 };
-static_assert(sizeof(PartialBary) == sizeof(PartialRec), "bary partials reuse the partial slots");
+// bytes per (split, output) slot of the partial buffer: the largest record
+constexpr int kPartialSlot = 24;
+static_assert(sizeof(PartialRec) <= kPartialSlot && sizeof(PartialCert) <= kPartialSlot &&
+                  sizeof(PartialBary) <= kPartialSlot, "every partial fits a slot");
 
 // What a sweep accumulates besides the shifted sum.
 enum SweepMode {
@@ -113,7 +127,8 @@ enum SweepMode {
 };
 
 struct Partials {
-  PartialRec* rec;  // [S][np]
+  void* rec;        // [S][np] records of the sweep's mode (PartialRec, PartialCert or PartialBary)
+  double* ref;      // [np] per-output reference R of the records (largest np of the two sides)
   int splits;       // allocated splits
 };
 

@@ -198,8 +198,8 @@ __device__ __forceinline__ void sweep_block(
     gfloat* __restrict__ out_abs, int np_out,
     gfloat* __restrict__ in_off, gfloat* __restrict__ in_A, gtile* __restrict__ in_tile,
     int ntiles_in, int count_in, int nsplit, const int* __restrict__ hint,
-    PartialRec* __restrict__ part, gctrl* __restrict__ ctrl, double eps_arg, int kofs, int bx, int split,
-    bool row_sweep, unsigned* __restrict__ tile_count, int slot) {
+    void* __restrict__ part, double* __restrict__ part_ref, gctrl* __restrict__ ctrl, double eps_arg, int kofs,
+    int bx, int split, bool row_sweep, unsigned* __restrict__ tile_count, int slot) {
   constexpr bool CERT = MODE == kSweepCert;
   constexpr bool BARY = MODE == kSweepBary;
   const int p = bx * kSweepBlock + threadIdx.x;
@@ -286,8 +286,27 @@ __device__ __forceinline__ void sweep_block(
       J = j;
     }
   }
+  // the records' reference: the warm start's exponent (the same in every
+  // split), 0 without one; split 0 stores it for the merge
+  const double Rref = M > -INFINITY ? M : 0.0;
+  if (!BARY && split == 0) part_ref[p] = Rref;
   float S = 0.0f, N = 0.0f;
   float V[D];
+  // writes this split's record: the shift relative to the reference in
+  // float32, the sums rescaled by that rounding so that the record is exact
+  auto write_rec = [&]() {
+    float dM = -INFINITY, fix = 1.0f;
+    if (M > -INFINITY) {
+      const double dd = M - Rref;
+      dM = (float)dd;
+      fix = fast_exp2((float)(dd - (double)dM));
+    }
+    if (CERT) {
+      reinterpret_cast<PartialCert*>(part)[(size_t)split * np_out + p] = PartialCert{dM, S * fix, N * fix, J};
+    } else {
+      reinterpret_cast<PartialRec*>(part)[(size_t)split * np_out + p] = PartialRec{dM, S * fix, J};
+    }
+  };
 #pragma unroll
   for (int d = 0; d < D; ++d) V[d] = 0.0f;
   int evaluated = 0;  // input tiles this wavefront evaluated (the same on every lane)
@@ -299,7 +318,7 @@ __device__ __forceinline__ void sweep_block(
       pb->S = S;
       for (int d = 0; d < 3; ++d) pb->V[d] = 0.0f;
     } else {
-      part[(size_t)split * np_out + p] = PartialRec{M, S, N, J, 0};
+      write_rec();
     }
     return;
   }
@@ -453,13 +472,7 @@ __device__ __forceinline__ void sweep_block(
     for (int d = 0; d < 3; ++d) pb->V[d] = d < D ? V[d] : 0.0f;
     return;
   }
-  PartialRec rec;
-  rec.M = M;
-  rec.S = S;
-  rec.N = CERT ? N : 0.0f;
-  rec.J = J;
-  rec.pad = 0;
-  part[(size_t)split * np_out + p] = rec;
+  write_rec();
 }
 
 template <int D, int MODE>
@@ -467,11 +480,16 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(
     const float* __restrict__ out_abs, int np_out,
     const float* __restrict__ in_off, const float* __restrict__ in_A, const TileRec* __restrict__ in_tile,
     int ntiles_in, int count_in, int nsplit, const int* __restrict__ hint,
-    PartialRec* __restrict__ part, const Ctrl* __restrict__ ctrl, double eps_arg, int kofs, int row_sweep,
-    unsigned* __restrict__ tile_count) {
+    void* __restrict__ part, double* __restrict__ part_ref, const Ctrl* __restrict__ ctrl, double eps_arg, int kofs,
+    int row_sweep, unsigned* __restrict__ tile_count) {
+  // blockIdx.x is the split and blockIdx.y the output block: consecutive
+  // workgroups go to consecutive XCDs, so the splits of one output block
+  // spread over all XCDs (a heavy output region does not load one XCD) and
+  // each XCD reads the input tiles of only splits / 8 splits (its L2 holds
+  // just those)
   const int slot = (blockIdx.y * gridDim.x + blockIdx.x) * (kSweepBlock / kTile) + threadIdx.x / kTile;
   sweep_block<D, MODE>((gfloat*)out_abs, np_out, (gfloat*)in_off, (gfloat*)in_A, (gtile*)in_tile, ntiles_in,
-                       count_in, nsplit, hint, part, (gctrl*)ctrl, eps_arg, kofs, blockIdx.x, blockIdx.y,
+                       count_in, nsplit, hint, part, part_ref, (gctrl*)ctrl, eps_arg, kofs, blockIdx.y, blockIdx.x,
                        row_sweep != 0, tile_count, slot);
 }
 
@@ -488,7 +506,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep_batch(const BatchItem* __
   const SideDev& in = transpose ? c.rows : c.cols;
   const int splits = transpose ? c.splits_col : c.splits_row;
   sweep_block<D, MODE>((gfloat*)out.abs, out.np, (gfloat*)in.off, (gfloat*)in.A, (gtile*)in.tile, in.ntiles,
-                       in.count, splits, out.hint, c.part.rec, (gctrl*)c.ctrl, -1.0, kofs, it.blk, it.split,
+                       in.count, splits, out.hint, c.part.rec, c.part.ref, (gctrl*)c.ctrl, -1.0, kofs, it.blk, it.split,
                        transpose == 0, nullptr, 0);
 }
 
@@ -502,38 +520,46 @@ struct Merged {
   int J;        // input slot of the exact maximum of the winning split, or -1
 };
 
-__device__ __forceinline__ Merged merge_splits(const PartialRec* __restrict__ part, int splits, int np,
-                                               int p) {
+template <typename Rec>
+__device__ __forceinline__ float rec_N(const Rec& q) { return 0.0f; }
+template <>
+__device__ __forceinline__ float rec_N<PartialCert>(const PartialCert& q) { return q.N; }
+
+template <typename Rec>
+__device__ __forceinline__ Merged merge_splits_t(const Rec* __restrict__ part, const double* __restrict__ ref,
+                                                 int splits, int np, int p) {
   // The epilogue runs few waves, so its time is the number of memory round
   // trips: one pass over the split records, G of them requested together.
-  // Past the last split the index is clamped to a valid record and its
-  // maximum gets -inf added (so its weight is 0): every loaded value is used
+  // Past the last split the index is clamped to a valid record and its shift
+  // gets -inf added (so its weight is 0): every loaded value is used
   // unconditionally, which keeps the loads together (a load the compiler may
   // sink under a branch waits for its data before the next one is issued).
-  // Each batch is merged against
-  // the running maximum, which is raised first if the batch holds a larger one
-  // (the running sums are rescaled).
+  // Each batch is merged against the running maximum, which is raised first
+  // if the batch holds a larger one (the running sums are rescaled).  Shifts
+  // are relative to the output's reference R.
   constexpr int G = 16;
-  double mx = -INFINITY, S = 0.0, N = 0.0;
+  const double R = ref[p];
+  float mx = -INFINITY;
+  double S = 0.0, N = 0.0;
   int J = -1;
   auto batch = [&](int s0) {
-    PartialRec q[G];
+    Rec q[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       q[g] = part[(size_t)min(s0 + g, splits - 1) * np + p];
-      q[g].M += (s0 + g < splits) ? 0.0 : -INFINITY;
+      q[g].dM += (s0 + g < splits) ? 0.0f : -INFINITY;
     }
-    double bm = -INFINITY;
+    float bm = -INFINITY;
     int bj = -1;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const bool up = q[g].M > bm;  // the first split holding the batch maximum
+      const bool up = q[g].dM > bm;  // the first split holding the batch maximum
       bj = up ? q[g].J : bj;
-      bm = up ? q[g].M : bm;
+      bm = up ? q[g].dM : bm;
     }
     if (bm > mx) {  // strictly: J stays with the first split holding the maximum
       // shifts of one output differ by little: the weight is a hardware float32 exp2
-      const double sc = mx == -INFINITY ? 0.0 : (double)fast_exp2((float)(mx - bm));
+      const double sc = mx == -INFINITY ? 0.0 : (double)fast_exp2(mx - bm);
       S *= sc;
       N *= sc;
       mx = bm;
@@ -542,9 +568,9 @@ __device__ __forceinline__ Merged merge_splits(const PartialRec* __restrict__ pa
     if (mx == -INFINITY) return;  // nothing so far
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const double w = (double)fast_exp2((float)(q[g].M - mx));  // 0 for an empty or masked split
+      const double w = (double)fast_exp2(q[g].dM - mx);  // 0 for an empty or masked split
       S += w * (double)q[g].S;
-      N += w * (double)q[g].N;
+      N += w * (double)rec_N(q[g]);
     }
   };
   // the first batch outside the loop: at a loop header the wait counts are
@@ -556,8 +582,13 @@ __device__ __forceinline__ Merged merge_splits(const PartialRec* __restrict__ pa
   r.S = S;
   r.N = N;
   r.J = J;
-  r.lse = kLn2D * (mx + log2(S));
+  r.lse = kLn2D * ((R + (double)mx) + log2(S));
   return r;
+}
+
+__device__ __forceinline__ Merged merge_splits(const Partials& pt, bool cert, int splits, int np, int p) {
+  if (cert) return merge_splits_t(reinterpret_cast<const PartialCert*>(pt.rec), pt.ref, splits, np, p);
+  return merge_splits_t(reinterpret_cast<const PartialRec*>(pt.rec), pt.ref, splits, np, p);
 }
 
 // Packs the weights w of one tile for the sweeps: a least-squares plane
@@ -690,7 +721,7 @@ struct MergedBary {
   double V[3];  // coordinate sums relative to the merged sum
 };
 
-__device__ __forceinline__ MergedBary merge_bary(const PartialRec* __restrict__ part, int splits, int np, int p) {
+__device__ __forceinline__ MergedBary merge_bary(const void* __restrict__ part, int splits, int np, int p) {
   const PartialBary* pb = reinterpret_cast<const PartialBary*>(part);
   double mx = -INFINITY;
   for (int s = 0; s < splits; ++s) mx = fmax(mx, pb[(size_t)s * np + p].M);
@@ -745,7 +776,9 @@ __device__ __forceinline__ void finish_block(const LaunchCtx& c, int transpose, 
   const double* t0_arr = transpose ? c.st.lt[0] : c.st.la;
   const double* t1_arr = transpose ? c.st.lt[1] : c.st.la;
   const double pre_lm = out.logmarg[p], pre_s = s_arr[p], pre_t0 = t0_arr[p], pre_t1 = t1_arr[p];
-  const Merged mg = merge_splits(c.part.rec, splits, np, p);
+  // the sweeps that gathered cost-weighted sums wrote certificate records
+  const bool cert_rec = kind == kFinishColCert || kind == kFinishCertOnly || kind == kFinishRound3;
+  const Merged mg = merge_splits(c.part, cert_rec, splits, np, p);
   // the warm start of the next sweep of this side: only the iteration's own sweeps set it
   if (real && iter_kind && mg.J >= 0) out.hint[p] = mg.J;
   const Ctrl* ctrl = &cv;
@@ -1425,18 +1458,18 @@ int choose_splits(int np_out, int ntiles_in) {
 hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int splits, double eps_arg, int kofs) {
   const SideDev& out = transpose ? c.cols : c.rows;
   const SideDev& in = transpose ? c.rows : c.cols;
-  dim3 grid(out.np / kSweepBlock, splits);
+  dim3 grid(splits, out.np / kSweepBlock);  // x: split, y: output block (see k_sweep)
 #define BDRS_SWEEP(DD, CC)                                                                             \
   if (c.ev_start && c.ev_stop)                                                                         \
     hipExtLaunchKernelGGL((k_sweep<DD, CC>), grid, dim3(kSweepBlock), 0, c.stream, c.ev_start, c.ev_stop, \
                           0u, (const float*)out.abs, (int)out.np, (const float*)in.off,                 \
                           (const float*)in.A, (const TileRec*)in.tile, (int)in.ntiles, (int)in.count,   \
-                          (int)splits, (const int*)out.hint, (PartialRec*)c.part.rec, (const Ctrl*)c.ctrl, \
+                          (int)splits, (const int*)out.hint, (void*)c.part.rec, (double*)c.part.ref, (const Ctrl*)c.ctrl, \
                           (double)eps_arg, (int)kofs, (int)(transpose ? 0 : 1), (unsigned*)c.tile_count);  \
   else                                                                                                 \
     hipLaunchKernelGGL((k_sweep<DD, CC>), grid, dim3(kSweepBlock), 0, c.stream, out.abs, out.np, in.off, \
                        in.A, in.tile, in.ntiles, in.count, splits, out.hint,                               \
-                       c.part.rec, c.ctrl, eps_arg, kofs, transpose ? 0 : 1, c.tile_count)
+                       c.part.rec, c.part.ref, c.ctrl, eps_arg, kofs, transpose ? 0 : 1, c.tile_count)
   switch (c.dim * 2 + (cert ? 1 : 0)) {
     case 2: BDRS_SWEEP(1, kSweepPlain); break;
     case 3: BDRS_SWEEP(1, kSweepCert); break;
@@ -1453,10 +1486,11 @@ hipError_t launch_sweep(const LaunchCtx& c, bool transpose, bool cert, int split
 hipError_t launch_sweep_bary(const LaunchCtx& c, int splits, double eps) {
   const SideDev& out = c.rows;
   const SideDev& in = c.cols;
-  dim3 grid(out.np / kSweepBlock, splits);
+  dim3 grid(splits, out.np / kSweepBlock);  // x: split, y: output block (see k_sweep)
 #define BDRS_SWEEP(DD)                                                                                  \
   hipLaunchKernelGGL((k_sweep<DD, kSweepBary>), grid, dim3(kSweepBlock), 0, c.stream, out.abs, out.np,   \
-                     in.off, in.A, in.tile, in.ntiles, in.count, splits, out.hint, c.part.rec, c.ctrl, eps, 0, 1,    \
+                     in.off, in.A, in.tile, in.ntiles, in.count, splits, out.hint, c.part.rec, c.part.ref, c.ctrl, eps, \
+                     0, 1, \
                      c.tile_count)
   switch (c.dim) {
     case 1: BDRS_SWEEP(1); break;

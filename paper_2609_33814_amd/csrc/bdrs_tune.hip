@@ -32,7 +32,7 @@ std::vector<int> split_candidates(int np_out, int ntiles_in) {
   for (long long s = 1; s <= ntiles_in && s <= 16LL * h; s *= 2) {
     if (16 * s < h) continue;
     const int v = normalize_splits((int)s, ntiles_in);
-    if ((size_t)v * (size_t)np_out * sizeof(PartialRec) <= kMaxPartialBytes) c.push_back(v);
+    if ((size_t)v * (size_t)np_out * kPartialSlot <= kMaxPartialBytes) c.push_back(v);
   }
   std::sort(c.begin(), c.end());
   c.erase(std::unique(c.begin(), c.end()), c.end());
