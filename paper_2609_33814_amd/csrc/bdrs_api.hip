@@ -80,11 +80,12 @@ Layout make_layout(int m, int n, int dim, int reserve_row, int reserve_col, bool
     return at;
   };
   L.ctrl = take(sizeof(Ctrl));
-  auto side = [&](const SideShape& s, size_t& abs, size_t& off, size_t& tile, size_t& A, size_t& perm,
-                  size_t& marg, size_t& logm, size_t& iperm, size_t& hint) {
+  auto side = [&](const SideShape& s, size_t& abs, size_t& off, size_t& tile, size_t& geom, size_t& A,
+                  size_t& perm, size_t& marg, size_t& logm, size_t& iperm, size_t& hint) {
     abs = take(sizeof(float) * (size_t)dim * s.np);
     off = take(sizeof(float) * (size_t)s.ntiles * dim * kTile);
     tile = take(sizeof(TileRec) * (size_t)s.ntiles);
+    geom = take(sizeof(TileGeom) * (size_t)s.ntiles);
     A = take(sizeof(float) * (size_t)s.np);
     perm = take(sizeof(int) * (size_t)s.np);
     marg = take(sizeof(double) * (size_t)s.np);
@@ -92,8 +93,8 @@ Layout make_layout(int m, int n, int dim, int reserve_row, int reserve_col, bool
     iperm = take(sizeof(int) * (size_t)s.count);
     hint = take(sizeof(int) * (size_t)s.np);
   };
-  side(L.R, L.r_abs, L.r_off, L.r_tile, L.r_A, L.r_perm, L.r_marg, L.r_logm, L.r_iperm, L.r_hint);
-  side(L.C, L.c_abs, L.c_off, L.c_tile, L.c_A, L.c_perm, L.c_marg, L.c_logm, L.c_iperm, L.c_hint);
+  side(L.R, L.r_abs, L.r_off, L.r_tile, L.r_geom, L.r_A, L.r_perm, L.r_marg, L.r_logm, L.r_iperm, L.r_hint);
+  side(L.C, L.c_abs, L.c_off, L.c_tile, L.c_geom, L.c_A, L.c_perm, L.c_marg, L.c_logm, L.c_iperm, L.c_hint);
   L.la = take(sizeof(double) * L.R.np);
   L.lah = take(sizeof(double) * L.R.np);
   L.lb1 = take(sizeof(double) * L.C.np);
@@ -271,6 +272,55 @@ void build_side(const float* pts, const double* w, int count, int dim, const dou
       hs.tile[t].rad[d] = rad;
     }
   }
+  // geometry of each tile's real points for the epilogues' plane fits, from
+  // the float32 offsets the device holds
+  hs.geom.assign((size_t)sh.ntiles, TileGeom{});
+  for (int t = 0; t < sh.ntiles; ++t) {
+    TileGeom& g = hs.geom[t];
+    const int s0 = t * kTile, n = std::min(count, s0 + kTile) - s0;
+    auto b = [&](int q, int d) { return (double)hs.off[((size_t)t * dim + d) * kTile + q]; };
+    g.cnt = (double)n;
+    for (int d = 0; d < dim; ++d) {
+      double s = 0.0;
+      for (int q = 0; q < n; ++q) s += b(q, d);
+      g.mb[d] = s / n;
+    }
+    double c[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int q = 0; q < n; ++q)
+      for (int d = 0; d < dim; ++d)
+        for (int e = 0; e < dim; ++e) c[d][e] += (b(q, d) - g.mb[d]) * (b(q, e) - g.mb[e]);
+    // inverse by cofactors; a (near-)singular matrix keeps the plane flat
+    double inv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    if (dim == 1) {
+      if (c[0][0] > 1e-12) inv[0][0] = 1.0 / c[0][0];
+    } else if (dim == 2) {
+      const double det = c[0][0] * c[1][1] - c[0][1] * c[1][0];
+      if (std::fabs(det) > 1e-12 * (c[0][0] * c[1][1] + 1e-300)) {
+        inv[0][0] = c[1][1] / det;
+        inv[1][1] = c[0][0] / det;
+        inv[0][1] = inv[1][0] = -c[0][1] / det;
+      }
+    } else {
+      const double a00 = c[1][1] * c[2][2] - c[1][2] * c[2][1];
+      const double a01 = c[0][2] * c[2][1] - c[0][1] * c[2][2];
+      const double a02 = c[0][1] * c[1][2] - c[0][2] * c[1][1];
+      const double det = c[0][0] * a00 + c[1][0] * a01 + c[2][0] * a02;
+      if (std::fabs(det) > 1e-12 * (c[0][0] * c[1][1] * c[2][2] + 1e-300)) {
+        inv[0][0] = a00 / det;
+        inv[0][1] = inv[1][0] = a01 / det;
+        inv[0][2] = inv[2][0] = a02 / det;
+        inv[1][1] = (c[0][0] * c[2][2] - c[0][2] * c[2][0]) / det;
+        inv[1][2] = inv[2][1] = (c[0][2] * c[1][0] - c[0][0] * c[1][2]) / det;
+        inv[2][2] = (c[0][0] * c[1][1] - c[0][1] * c[1][0]) / det;
+      }
+    }
+    g.cinv[0] = inv[0][0];
+    g.cinv[1] = inv[0][1];
+    g.cinv[2] = inv[0][2];
+    g.cinv[3] = inv[1][1];
+    g.cinv[4] = inv[1][2];
+    g.cinv[5] = inv[2][2];
+  }
 }
 
 
@@ -284,8 +334,8 @@ void fill_ctx(bdrs_solver s) {
   c.splits_row = L.splits_row;
   c.splits_col = L.splits_col;
   c.ctrl = (Ctrl*)(base + L.ctrl);
-  auto side = [&](SideDev& sd, const SideShape& sh, size_t abs, size_t off, size_t tile, size_t A, size_t perm,
-                  size_t marg, size_t logm, size_t iperm, size_t hint) {
+  auto side = [&](SideDev& sd, const SideShape& sh, size_t abs, size_t off, size_t tile, size_t geom, size_t A,
+                  size_t perm, size_t marg, size_t logm, size_t iperm, size_t hint) {
     sd.count = sh.count;
     sd.ntiles = sh.ntiles;
     sd.np = sh.np;
@@ -293,6 +343,7 @@ void fill_ctx(bdrs_solver s) {
     sd.abs = (float*)(base + abs);
     sd.off = (float*)(base + off);
     sd.tile = (TileRec*)(base + tile);
+    sd.geom = (const TileGeom*)(base + geom);
     sd.A = (float*)(base + A);
     sd.perm = (int*)(base + perm);
     sd.marg = (double*)(base + marg);
@@ -300,8 +351,10 @@ void fill_ctx(bdrs_solver s) {
     sd.iperm = (int*)(base + iperm);
     sd.hint = (int*)(base + hint);
   };
-  side(c.rows, L.R, L.r_abs, L.r_off, L.r_tile, L.r_A, L.r_perm, L.r_marg, L.r_logm, L.r_iperm, L.r_hint);
-  side(c.cols, L.C, L.c_abs, L.c_off, L.c_tile, L.c_A, L.c_perm, L.c_marg, L.c_logm, L.c_iperm, L.c_hint);
+  side(c.rows, L.R, L.r_abs, L.r_off, L.r_tile, L.r_geom, L.r_A, L.r_perm, L.r_marg, L.r_logm, L.r_iperm,
+       L.r_hint);
+  side(c.cols, L.C, L.c_abs, L.c_off, L.c_tile, L.c_geom, L.c_A, L.c_perm, L.c_marg, L.c_logm, L.c_iperm,
+       L.c_hint);
   c.st.la = (double*)(base + L.la);
   c.st.lah = (double*)(base + L.lah);
   c.st.lb1 = (double*)(base + L.lb1);
@@ -965,6 +1018,7 @@ bdrs_status create_from_image(const bdrs_params* p, const HostImage& img, bdrs_s
   chk(up(c.rows.abs, R.abs.data(), R.abs.size() * sizeof(float)));
   chk(up(c.rows.off, R.off.data(), R.off.size() * sizeof(float)));
   chk(up(c.rows.tile, R.tile.data(), R.tile.size() * sizeof(TileRec)));
+  chk(up((void*)c.rows.geom, R.geom.data(), R.geom.size() * sizeof(TileGeom)));
   chk(up(c.rows.perm, R.perm.data(), R.perm.size() * sizeof(int)));
   chk(up(c.rows.iperm, R.iperm.data(), R.iperm.size() * sizeof(int)));
   chk(up(c.cols.iperm, C.iperm.data(), C.iperm.size() * sizeof(int)));
@@ -975,6 +1029,7 @@ bdrs_status create_from_image(const bdrs_params* p, const HostImage& img, bdrs_s
   chk(up(c.cols.abs, C.abs.data(), C.abs.size() * sizeof(float)));
   chk(up(c.cols.off, C.off.data(), C.off.size() * sizeof(float)));
   chk(up(c.cols.tile, C.tile.data(), C.tile.size() * sizeof(TileRec)));
+  chk(up((void*)c.cols.geom, C.geom.data(), C.geom.size() * sizeof(TileGeom)));
   chk(up(c.cols.perm, C.perm.data(), C.perm.size() * sizeof(int)));
   chk(up(c.cols.marg, C.marg.data(), C.marg.size() * sizeof(double)));
   chk(up(c.cols.logmarg, C.logm.data(), C.logm.size() * sizeof(double)));

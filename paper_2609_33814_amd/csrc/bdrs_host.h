@@ -29,8 +29,8 @@ struct Layout {
   size_t total;
   // offsets
   size_t ctrl;
-  size_t r_abs, r_off, r_tile, r_A, r_perm, r_marg, r_logm, r_iperm, r_hint;
-  size_t c_abs, c_off, c_tile, c_A, c_perm, c_marg, c_logm, c_iperm, c_hint;
+  size_t r_abs, r_off, r_tile, r_geom, r_A, r_perm, r_marg, r_logm, r_iperm, r_hint;
+  size_t c_abs, c_off, c_tile, c_geom, c_A, c_perm, c_marg, c_logm, c_iperm, c_hint;
   size_t la, lah, lb1, lb2, lbh, lt0, lt1, mu, logs, pvec;
   size_t part, part_ref, cert_part, cert_out, plan_row, plan_col, plan_aux, plan_stats, tile_count, tile_total;
   // retained best state (BDRS_F_KEEP_BEST_STATE; 0 otherwise), in tile order
@@ -55,6 +55,7 @@ bdrs_status check_device();
 struct HostSide {
   std::vector<float> abs, off;
   std::vector<TileRec> tile;
+  std::vector<TileGeom> geom;
   std::vector<int> perm, iperm;
   std::vector<double> marg, logm;
 };

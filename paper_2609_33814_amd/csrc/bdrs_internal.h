@@ -53,6 +53,18 @@ struct alignas(64) TileRec {
 };
 static_assert(sizeof(TileRec) == 64, "one scalar dwordx16 load per tile");
 
+// Geometry of one tile's real points, fixed for a solve: the epilogues fit a
+// plane to the tile's log weights over these offsets, and with every real
+// point live (the marginals are positive) the fit needs only the weighted
+// sums.  cinv holds the inverse of the centred scatter matrix sum (b - mb)
+// (b - mb)^T (entries xx, xy, xz, yy, yz, zz; all 0 when it is near singular:
+// then the plane is flat).
+struct TileGeom {
+  double mb[3];    // mean offset of the real points
+  double cinv[6];
+  double cnt;      // real points
+};
+
 // One point set stored in tile order.  Slot p holds original point perm[p];
 // slots >= count are padding (copies of a real point with weight -inf).
 struct SideDev {
@@ -65,6 +77,7 @@ struct SideDev {
   float* A;        // [np] log2 weights of the next sweep that reads this side minus their
                    //      tile's plane fit and the tile-local quadratic (float32)
   TileRec* tile;   // [ntiles] per-tile record (maximum, plane fit, centre, radius)
+  const TileGeom* geom;  // [ntiles] geometry of the real points
   int* perm;       // [np] original index of each slot
   int* iperm;      // [count] slot of each original index
   int* hint;       // [np] warm start of the sweep with this side as output: the slot of an

@@ -114,6 +114,21 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
+// N independent sums at once (their lane moves interleave).
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<kDppXor1>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<kDppXor2>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<kDppHalfMirror>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<kDppMirror>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = (read_lane(v[i], 0) + read_lane(v[i], 16)) + (read_lane(v[i], 32) + read_lane(v[i], 48));
+}
+
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_move<kDppXor1>(v));
   v = fmax(v, dpp_move<kDppXor2>(v));
@@ -635,54 +650,83 @@ __device__ __forceinline__ void pack_weight_d(const SideDev& sd, int p, double w
   }
   if (p >= sd.ntiles * kTile) return;
   const double m = wave_max(A);
-  // least-squares plane through the live points of the tile (centred sums)
-  const double one = live ? 1.0 : 0.0;
-  const double cnt = wave_sum(one);
-  double mb[D], mw = 0.0;
-#pragma unroll
-  for (int d = 0; d < D; ++d) mb[d] = 0.0;
   double gam[3] = {0.0, 0.0, 0.0}, alpha = -INFINITY;
-  if (cnt > 0.0) {
-    for (int d = 0; d < dim; ++d) mb[d] = wave_sum(one * b[d]) / cnt;
-    mw = wave_sum(live ? w2 : 0.0) / cnt;
-    double cbb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, cbw[3] = {0, 0, 0};
-    for (int d = 0; d < dim; ++d) {
-      const double bd = live ? b[d] - mb[d] : 0.0;
-      cbw[d] = wave_sum(bd * (live ? w2 - mw : 0.0));
-      for (int e = 0; e <= d; ++e) {
-        cbb[d][e] = wave_sum(bd * (live ? b[e] - mb[e] : 0.0));
-        cbb[e][d] = cbb[d][e];
-      }
-    }
-    // solve cbb gamma = cbw by Cramer's rule; a (near-)singular system keeps gamma = 0
-    if constexpr (D == 1) {
-      if (cbb[0][0] > 1e-12) gam[0] = cbw[0] / cbb[0][0];
-    } else if constexpr (D == 2) {
-      const double det = cbb[0][0] * cbb[1][1] - cbb[0][1] * cbb[1][0];
-      if (fabs(det) > 1e-12 * (cbb[0][0] * cbb[1][1] + 1e-300)) {
-        gam[0] = (cbw[0] * cbb[1][1] - cbb[0][1] * cbw[1]) / det;
-        gam[1] = (cbb[0][0] * cbw[1] - cbw[0] * cbb[1][0]) / det;
-      }
-    } else {
-      const double a00 = cbb[1][1] * cbb[2][2] - cbb[1][2] * cbb[2][1];
-      const double a01 = cbb[0][2] * cbb[2][1] - cbb[0][1] * cbb[2][2];
-      const double a02 = cbb[0][1] * cbb[1][2] - cbb[0][2] * cbb[1][1];
-      const double det = cbb[0][0] * a00 + cbb[1][0] * a01 + cbb[2][0] * a02;
-      if (fabs(det) > 1e-12 * (cbb[0][0] * cbb[1][1] * cbb[2][2] + 1e-300)) {
-        const double a10 = cbb[1][2] * cbb[2][0] - cbb[1][0] * cbb[2][2];
-        const double a11 = cbb[0][0] * cbb[2][2] - cbb[0][2] * cbb[2][0];
-        const double a12 = cbb[0][2] * cbb[1][0] - cbb[0][0] * cbb[1][2];
-        const double a20 = cbb[1][0] * cbb[2][1] - cbb[1][1] * cbb[2][0];
-        const double a21 = cbb[0][1] * cbb[2][0] - cbb[0][0] * cbb[2][1];
-        const double a22 = cbb[0][0] * cbb[1][1] - cbb[0][1] * cbb[1][0];
-        gam[0] = (a00 * cbw[0] + a01 * cbw[1] + a02 * cbw[2]) / det;
-        gam[1] = (a10 * cbw[0] + a11 * cbw[1] + a12 * cbw[2]) / det;
-        gam[2] = (a20 * cbw[0] + a21 * cbw[1] + a22 * cbw[2]) / det;
-      }
-    }
-    for (int d = 0; d < dim; ++d) gam[d] = (double)(float)gam[d];  // the sweep reads gamma as float32
+  // least-squares plane through the live points of the tile (centred sums).
+  // When the live points are the tile's real points (every weight finite, as
+  // in the iterations: the marginals are positive), their geometry is the
+  // tile's precomputed one and the fit needs only the sums of w2 and of the
+  // centred offsets times w2 (the centred offsets sum to zero, so the latter
+  // is the centred cross sum), all taken at once.
+  const int nreal = min(kTile, sd.count - t * kTile);
+  const unsigned long long real_mask = nreal >= kTile ? ~0ull : ((1ull << nreal) - 1ull);
+  if (__ballot(live) == real_mask) {
+    const TileGeom* g = sd.geom + t;
+    const double wl = live ? w2 : 0.0;
+    double v[D + 1];
+    v[0] = wl;
+#pragma unroll
+    for (int d = 0; d < D; ++d) v[d + 1] = live ? (b[d] - g->mb[d]) * wl : 0.0;
+    wave_sum_n<D + 1>(v);
+    const double mw = v[0] / g->cnt;
+    // symmetric inverse stored as xx, xy, xz, yy, yz, zz
+    constexpr int kSym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
     alpha = mw;
-    for (int d = 0; d < dim; ++d) alpha -= gam[d] * mb[d];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      double s = 0.0;
+#pragma unroll
+      for (int e = 0; e < D; ++e) s = fma(g->cinv[kSym[d][e]], v[e + 1], s);
+      gam[d] = (double)(float)s;  // the sweep reads gamma as float32
+      alpha -= gam[d] * g->mb[d];
+    }
+  } else {
+    const double one = live ? 1.0 : 0.0;
+    const double cnt = wave_sum(one);
+    double mb[D], mw = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) mb[d] = 0.0;
+    if (cnt > 0.0) {
+      for (int d = 0; d < dim; ++d) mb[d] = wave_sum(one * b[d]) / cnt;
+      mw = wave_sum(live ? w2 : 0.0) / cnt;
+      double cbb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, cbw[3] = {0, 0, 0};
+      for (int d = 0; d < dim; ++d) {
+        const double bd = live ? b[d] - mb[d] : 0.0;
+        cbw[d] = wave_sum(bd * (live ? w2 - mw : 0.0));
+        for (int e = 0; e <= d; ++e) {
+          cbb[d][e] = wave_sum(bd * (live ? b[e] - mb[e] : 0.0));
+          cbb[e][d] = cbb[d][e];
+        }
+      }
+      // solve cbb gamma = cbw by Cramer's rule; a (near-)singular system keeps gamma = 0
+      if constexpr (D == 1) {
+        if (cbb[0][0] > 1e-12) gam[0] = cbw[0] / cbb[0][0];
+      } else if constexpr (D == 2) {
+        const double det = cbb[0][0] * cbb[1][1] - cbb[0][1] * cbb[1][0];
+        if (fabs(det) > 1e-12 * (cbb[0][0] * cbb[1][1] + 1e-300)) {
+          gam[0] = (cbw[0] * cbb[1][1] - cbb[0][1] * cbw[1]) / det;
+          gam[1] = (cbb[0][0] * cbw[1] - cbw[0] * cbb[1][0]) / det;
+        }
+      } else {
+        const double a00 = cbb[1][1] * cbb[2][2] - cbb[1][2] * cbb[2][1];
+        const double a01 = cbb[0][2] * cbb[2][1] - cbb[0][1] * cbb[2][2];
+        const double a02 = cbb[0][1] * cbb[1][2] - cbb[0][2] * cbb[1][1];
+        const double det = cbb[0][0] * a00 + cbb[1][0] * a01 + cbb[2][0] * a02;
+        if (fabs(det) > 1e-12 * (cbb[0][0] * cbb[1][1] * cbb[2][2] + 1e-300)) {
+          const double a10 = cbb[1][2] * cbb[2][0] - cbb[1][0] * cbb[2][2];
+          const double a11 = cbb[0][0] * cbb[2][2] - cbb[0][2] * cbb[2][0];
+          const double a12 = cbb[0][2] * cbb[1][0] - cbb[0][0] * cbb[1][2];
+          const double a20 = cbb[1][0] * cbb[2][1] - cbb[1][1] * cbb[2][0];
+          const double a21 = cbb[0][1] * cbb[2][0] - cbb[0][0] * cbb[2][1];
+          const double a22 = cbb[0][0] * cbb[1][1] - cbb[0][1] * cbb[1][0];
+          gam[0] = (a00 * cbw[0] + a01 * cbw[1] + a02 * cbw[2]) / det;
+          gam[1] = (a10 * cbw[0] + a11 * cbw[1] + a12 * cbw[2]) / det;
+          gam[2] = (a20 * cbw[0] + a21 * cbw[1] + a22 * cbw[2]) / det;
+        }
+      }
+      for (int d = 0; d < dim; ++d) gam[d] = (double)(float)gam[d];  // the sweep reads gamma as float32
+      alpha = mw;
+      for (int d = 0; d < dim; ++d) alpha -= gam[d] * mb[d];
+    }
   }
   double res = 0.0;
   if (live) {
