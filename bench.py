@@ -40,30 +40,30 @@ EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters
                      # 64 lane-ops/CU/cycle ceiling, which a 2-slot exp would put above 100%
 
 
-# HBM traffic of one k_sweep<2,0> launch on the 128x128 grids (16 splits per
-# direction), averaged over the profiled replay of the default run (k = 150 ...
-# 1149): rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by
-# what the counter reads for a 256 MiB device copy (x2.000 and x1.000).  It
-# holds for the kernel sources with this sha256 (of bdrs_kernels.hip followed
-# by bdrs_internal.h) and that split count only; otherwise it is reported as
-# null.
-TRAFFIC_KERNEL_SHA256 = "237cbb8703d376621f0b7e214819cfc643498810db036812f95cf7b856330d05"
-TRAFFIC_SPLITS = 16
-TRAFFIC_BYTES_PER_LAUNCH = 6.84e6
+# HBM traffic of one k_sweep<2,0> launch on the 128x128 grids (16 row and 8
+# column splits), averaged over the row and column sweeps of the profiled
+# replay of the default run (k = 150 ... 1149): rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE per dispatch, each scaled by what the counter reads for a 256 MiB
+# device copy (x2.000 and x1.000).  It holds for the kernel sources with this
+# sha256 (of bdrs_kernels.hip followed by bdrs_internal.h) and those split
+# counts only; otherwise it is reported as null.
+TRAFFIC_KERNEL_SHA256 = "69aece34765ef2baa384c8c09d366a4fcf503e043b479c62474d50b76578320f"
+TRAFFIC_SPLITS = (16, 8)
+TRAFFIC_BYTES_PER_LAUNCH = 5.70e6
 # Counters of the same profile (per dispatch of k_sweep<2,0> in the replay):
 # VALU lane instructions and v_exp_f32 per evaluated entry (x 64 / evaluated
 # entries), VALU issue utilisation (lane instructions / duration / (256 x 64 x
 # 2.4 GHz)) and rocprof's VALUBusy.
-PROFILE_COUNTERS = {"valu_instr_per_evaluated_entry": 8.19, "exp_per_evaluated_entry": 1.007,
-                    "valu_issue_frac": 0.294, "VALUBusy": 19.6,
+PROFILE_COUNTERS = {"valu_instr_per_evaluated_entry": 9.62, "exp_per_evaluated_entry": 1.017,
+                    "valu_issue_frac": 0.387, "VALUBusy": 23.1,
                     "source": "profiles/k_sweep_grid128x128.md"}
 
 
-def profiled_counters(splits_row: int):
-    return PROFILE_COUNTERS if measured_traffic(splits_row) is not None else None
+def profiled_counters(splits):
+    return PROFILE_COUNTERS if measured_traffic(splits) is not None else None
 
 
-def measured_traffic(splits_row: int):
+def measured_traffic(splits):
     import hashlib
     m = hashlib.sha256()
     try:
@@ -72,7 +72,7 @@ def measured_traffic(splits_row: int):
     except OSError:
         return None
     sha = m.hexdigest()
-    if sha != TRAFFIC_KERNEL_SHA256 or splits_row != TRAFFIC_SPLITS:
+    if sha != TRAFFIC_KERNEL_SHA256 or splits != TRAFFIC_SPLITS:
         return None
     return TRAFFIC_BYTES_PER_LAUNCH
 
@@ -612,7 +612,7 @@ def main() -> int:
 
     sv = bdrs.Solver(X, Y, R, C, prob.cost_scale, eta=ETA, lam=args.lam)
     tuned = [e for e in bdrs.tune_table() if (e["dim"], e["m"], e["n"]) == (prob.dim, prob.m, prob.n)]
-    splits_row = tuned[0]["splits_row"] if tuned else None
+    splits = (tuned[0]["splits_row"], tuned[0]["splits_col"]) if tuned else None
     for _ in range(args.warmup):
         sv.solve(0.0, CERT_EVERY, CERT_EVERY)
     torch.cuda.synchronize()
@@ -706,13 +706,13 @@ def main() -> int:
                    "last_rel_gap": last["rel_gap"] if last else None},
         "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 2),
                      "unit": "Gentries/s", "frac": round(achieved / peak, 4),
-                     "traffic": measured_traffic(splits_row), "traffic_unit": "HBM bytes per launch",
+                     "traffic": measured_traffic(splits), "traffic_unit": "HBM bytes per launch",
                      "kernel": "k_sweep<2,0> (plain mode)", "per_launch_us": round(per_sweep_ms * 1e3, 3),
-                     "splits": splits_row,
+                     "splits": list(splits) if splits else None,
                      "implicit_gentries_per_s": round(implicit_rate, 2),
                      "evaluated_fraction": round(evaluated_frac, 4),
                      "exp_per_s": round(achieved * 1e9, 0),  # one v_exp_f32 per evaluated entry
-                     "counters": profiled_counters(splits_row)},
+                     "counters": profiled_counters(splits)},
         "cpu_baseline": cpu,
         "time_to_1pct": ttg,
         "batch": batch,
