@@ -35,8 +35,8 @@ CERT_EVERY = 50
 # problem has 4.3e9; the GPU is saturated well below that) run one at a time.
 BIG_WORK = 1e9
 CU, LANES, CLK = 256, 64, 2.4e9
-EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters show 6.78 VALU
-                     # instructions per entry (one of them the exp) issued at 95% of the
+EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters show 6.80 VALU
+                     # instructions per entry (one of them the exp) issued at 98% of the
                      # 64 lane-ops/CU/cycle ceiling, which a 2-slot exp would put above 100%
 
 
