@@ -40,7 +40,7 @@ EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters
                      # 64 lane-ops/CU/cycle ceiling, which a 2-slot exp would put above 100%
 
 
-# HBM traffic of one k_sweep<2,0> launch on the 128x128 grids (16 row and 8
+# HBM traffic of one k_sweep<2,0> launch on the 128x128 grids (16 row and 16
 # column splits), averaged over the row and column sweeps of the profiled
 # replay of the default run (k = 150 ... 1149): rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE per dispatch, each scaled by what the counter reads for a 256 MiB
@@ -48,14 +48,14 @@ EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters
 # sha256 (of bdrs_kernels.hip followed by bdrs_internal.h) and those split
 # counts only; otherwise it is reported as null.
 TRAFFIC_KERNEL_SHA256 = "69aece34765ef2baa384c8c09d366a4fcf503e043b479c62474d50b76578320f"
-TRAFFIC_SPLITS = (16, 8)
-TRAFFIC_BYTES_PER_LAUNCH = 5.70e6
+TRAFFIC_SPLITS = (16, 16)
+TRAFFIC_BYTES_PER_LAUNCH = 6.41e6
 # Counters of the same profile (per dispatch of k_sweep<2,0> in the replay):
 # VALU lane instructions and v_exp_f32 per evaluated entry (x 64 / evaluated
 # entries), VALU issue utilisation (lane instructions / duration / (256 x 64 x
 # 2.4 GHz)) and rocprof's VALUBusy.
-PROFILE_COUNTERS = {"valu_instr_per_evaluated_entry": 9.62, "exp_per_evaluated_entry": 1.017,
-                    "valu_issue_frac": 0.387, "VALUBusy": 23.1,
+PROFILE_COUNTERS = {"valu_instr_per_evaluated_entry": 10.98, "exp_per_evaluated_entry": 1.023,
+                    "valu_issue_frac": 0.426, "VALUBusy": 26.3,
                     "source": "profiles/k_sweep_grid128x128.md"}
 
 
