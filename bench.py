@@ -47,7 +47,7 @@ EXP_SLOTS = 1        # issue slots of one v_exp_f32: the colour sweep's counters
 # device copy (x2.000 and x1.000).  It holds for the kernel sources with this
 # sha256 (of bdrs_kernels.hip followed by bdrs_internal.h) and those split
 # counts only; otherwise it is reported as null.
-TRAFFIC_KERNEL_SHA256 = "69aece34765ef2baa384c8c09d366a4fcf503e043b479c62474d50b76578320f"
+TRAFFIC_KERNEL_SHA256 = "633d46953d215f376c287b60b5ff776a06218199df7e69343cad1dca31ba95eb"
 TRAFFIC_SPLITS = (16, 16)
 TRAFFIC_BYTES_PER_LAUNCH = 6.41e6
 # Counters of the same profile (per dispatch of k_sweep<2,0> in the replay):

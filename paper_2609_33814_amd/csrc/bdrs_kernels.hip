@@ -126,7 +126,8 @@ __device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
 #pragma unroll
   for (int i = 0; i < N; ++i) v[i] += dpp_move<kDppMirror>(v[i]);
 #pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = (read_lane(v[i], 0) + read_lane(v[i], 16)) + (read_lane(v[i], 32) + read_lane(v[i], 48));
+  for (int i = 0; i < N; ++i)
+    v[i] = (read_lane(v[i], 0) + read_lane(v[i], 16)) + (read_lane(v[i], 32) + read_lane(v[i], 48));
 }
 
 __device__ __forceinline__ double wave_max(double v) {
